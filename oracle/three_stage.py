@@ -1,0 +1,270 @@
+"""Oracle (test infrastructure only): the three-stage algorithm (Alg. 4) in FP64.
+
+Alg. 2 (initial interval from extreme Ritz values), Alg. 1' (bisection with a
+sparse LDL^T inertia count) and Alg. 3 (shift-and-invert Lanczos with error
+bounds, Prop. 3), written from the paper's description over the plain-C
+sparse oracle for nu(sigma) and the linear solves, and scipy's CSR product for
+A x and B x.  Readings of points the paper leaves open:
+
+* starting vectors come from ``pencilgen.start_vectors`` (row 0: stage 1,
+  row 1: stage 3, later rows: restarts after a breakdown);
+* both Lanczos processes use full two-pass classical Gram-Schmidt
+  reorthogonalisation in their inner product;
+* the SI basis is kept as V = B^{-1} V~ (B-orthonormal) together with V~ = B V,
+  so B^{-1} is never applied; x_{i,2} = theta_i V y_i + beta_j (e_j^T y_i) v_{j+1},
+  which equals (A - sigma B)^{-1} V~ y_i by the SI Lanczos decomposition;
+* the m pairs nearest sigma are those with the largest |theta~| (ties: larger
+  theta~ first); inclusion uses the closed bound inside [sigma_l, sigma_u);
+* relative differences pair the m validated vectors of consecutive iterations in
+  ascending eigenvalue order, after scaling to unit 2-norm and aligning signs;
+* the residual test uses eq. (res2): ||r_{i,2}|| = |s_i| ||v~_{j+1}||;
+* the returned vector is B-normalised with its largest-|.| entry positive.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+import pencilgen
+from . import sparse as osp
+
+
+@dataclasses.dataclass
+class Result:
+    lam: float
+    x: np.ndarray
+    k_validated: int
+    sigma_lower: float
+    sigma_upper: float
+    nu_lower: int
+    nu_upper: int
+    sigma_si: float
+    stage1_steps: int
+    bisection_steps: int
+    si_steps: int
+    it_bound: int
+    it_residual: int
+    it_difference: int
+    sigmas: list          # every shift whose inertia was computed, in order
+    nus: list
+    rel_residual: float   # ||(A - lam B) x||_2 / ||x||_2 with explicit products
+    n_factorizations: int
+
+
+class NoConvergence(RuntimeError):
+    pass
+
+
+def _bnorm(Bx, x):
+    return float(np.sqrt(np.dot(x, Bx)))
+
+
+def _tridiag_eig(alpha, beta):
+    T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+    return np.linalg.eigh(T)
+
+
+def stage1(pencil, k, P, A, B, Bfac, v0s, nu_of, log):
+    """Alg. 2: returns sigma_l, sigma_u, nu_l, nu_u, steps."""
+    restart = 0
+    v = v0s[0].copy()
+    Bv = B @ v
+    nb = _bnorm(Bv, v)
+    V, BV = [v / nb], [Bv / nb]
+    alphas, betas = [], []
+    sig_prev, nu_prev = None, 0
+    j = 0
+    while True:
+        j += 1
+        vj, Bvj = V[-1], BV[-1]
+        Av = A @ vj
+        alphas.append(float(np.dot(vj, Av)))
+        w = Bfac.solve(Av)       # B^{-1} A v_j
+        Bw = Av.copy()
+        Vm, BVm = np.array(V).T, np.array(BV).T
+        for _ in range(2):       # CGS2 in the B inner product
+            h = Vm.T @ Bw
+            w -= Vm @ h
+            Bw -= BVm @ h
+        theta = np.linalg.eigvalsh(np.diag(alphas) + np.diag(betas, 1) + np.diag(betas, -1))
+        sig = float(theta[0]) if k <= nu_prev else float(theta[-1])
+        nu = nu_of(sig)
+        log.append((sig, nu))
+        if j != 1 and (nu < k <= nu_prev or nu_prev < k <= nu):
+            return min(sig_prev, sig), max(sig_prev, sig), min(nu_prev, nu), max(nu_prev, nu), j
+        sig_prev, nu_prev = sig, nu
+        beta = _bnorm(Bw, w)
+        if beta <= 1e-14 * max(1.0, abs(alphas[-1])):
+            # breakdown: restart with the next seeded vector
+            restart += 1
+            if restart >= v0s.shape[0] - 1:
+                raise NoConvergence("stage-1 Lanczos broke down repeatedly")
+            v = v0s[1 + restart].copy()
+            Bv = B @ v
+            nb = _bnorm(Bv, v)
+            V, BV = [v / nb], [Bv / nb]
+            alphas, betas = [], []
+            sig_prev, nu_prev, j = None, 0, 0
+            continue
+        betas.append(beta)
+        V.append(w / beta)
+        BV.append(Bw / beta)
+        if j > P.n + 1:
+            raise NoConvergence("stage-1 exceeded n steps")
+
+
+def stage2(k, sl, su, nl, nu_, nu_of, log, m_max=20, tau_len=0.0):
+    """Alg. 1': bisection until nu_u - nu_l <= m_max (repeat-until, i.e. at least
+    one step), or the interval is shorter than tau_len (cluster guard)."""
+    steps = 0
+    while True:
+        sig = 0.5 * (sl + su)
+        nu = nu_of(sig)
+        log.append((sig, nu))
+        steps += 1
+        if k <= nu:
+            su, nu_ = sig, nu
+        else:
+            sl, nl = sig, nu
+        if nu_ - nl <= m_max:
+            break
+        if tau_len > 0 and (su - sl) < tau_len:
+            break
+    return sl, su, nl, nu_, steps
+
+
+def alg1_bisection(k, sl, su, nu_of, tau=None, rel_tau=None):
+    """Alg. 1: plain spectral bisection until the interval is shorter than tau
+    (absolute), or, as in the straightforward variant of Section 4.3.2, until
+    (sigma_u - sigma_l) / max(|sigma_l|, |sigma_u|) < rel_tau.  Returns the
+    midpoint estimate, the final interval and the number of steps."""
+    steps = 0
+    while True:
+        w = su - sl
+        if tau is not None and w < tau:
+            break
+        if rel_tau is not None and w / max(abs(sl), abs(su)) < rel_tau:
+            break
+        sig = 0.5 * (sl + su)
+        if k <= nu_of(sig):
+            su = sig
+        else:
+            sl = sig
+        steps += 1
+    return 0.5 * (sl + su), sl, su, steps
+
+
+def stage3(pencil, k, sl, su, nl, nu_, A, B, v0, tau_res=1e-10, tau_diff=1e-10,
+           max_iter=500, factor=None, trace=None):
+    """Alg. 3: shift-and-invert Lanczos at the midpoint with validated index.
+    ``trace`` (optional) is called at every iteration j >= m with the Ritz data."""
+    l = k - nl
+    m = nu_ - nl
+    sigma = 0.5 * (sl + su)
+    F = factor if factor is not None else osp.Factor(pencil, sigma)
+    v = v0.copy()
+    Bv = B @ v
+    nb = _bnorm(Bv, v)
+    V, Vt = [v / nb], [Bv / nb]             # V = B^{-1} V~, V~ = B V
+    alphas, betas = [], []
+    prev = None
+    it_bound = it_res = it_diff = 0
+    for j in range(1, max_iter + 1):
+        w = F.solve(Vt[-1])                  # (A - sigma B)^{-1} v~_j
+        Bw = B @ w
+        Vm, Vtm = np.array(V).T, np.array(Vt).T
+        h = Vtm.T @ w                        # = V^T B w
+        alphas.append(float(h[-1]))
+        w -= Vm @ h
+        Bw -= Vtm @ h
+        h2 = Vtm.T @ w
+        w -= Vm @ h2
+        Bw -= Vtm @ h2
+        beta = float(np.sqrt(max(np.dot(w, Bw), 0.0)))
+        if beta > 0:
+            vnext, vtnext = w / beta, Bw / beta
+        else:
+            vnext, vtnext = np.zeros_like(w), np.zeros_like(w)
+        if j >= m:
+            th, Y = _tridiag_eig(np.array(alphas), np.array(betas))
+            order = sorted(range(j), key=lambda i: (-abs(th[i]), -th[i]))[:m]
+            lam = sigma + 1.0 / th[order]
+            s = beta * Y[-1, order] / th[order]
+            eta = (1.0 / np.abs(th[order])) * np.abs(s) / np.sqrt(1.0 + s * s)
+            X = Vm @ (Y[:, order] * th[order]) + np.outer(vnext, beta * Y[-1, order])
+            incl = bool(np.all(lam - eta >= sl) and np.all(lam + eta < su))
+            asc = np.argsort(lam, kind="stable")
+            lo, hi = (lam - eta)[asc], (lam + eta)[asc]
+            disj = bool(np.all(hi[:-1] < lo[1:]))
+            xn = np.linalg.norm(X, axis=0)
+            rres = np.abs(s) * np.linalg.norm(vtnext) / xn
+            res_ok = bool(np.all(rres < tau_res))
+            Xa = X[:, asc] / xn[asc]
+            if prev is not None:
+                sg = np.sign(np.sum(Xa * prev, axis=0))
+                sg[sg == 0] = 1.0
+                diff = np.linalg.norm(Xa * sg - prev, axis=0)
+                diff_ok = bool(np.all(diff < tau_diff))
+            else:
+                diff_ok = False
+            prev = Xa
+            if trace is not None:
+                trace(dict(j=j, sigma=sigma, theta=th, Y=Y, order=order, lam=lam, eta=eta,
+                           s=s, X=X, V=Vm, Vt=Vtm, vnext=vnext, vtnext=vtnext, beta=beta,
+                           incl=incl, disj=disj, res_ok=res_ok, diff_ok=diff_ok))
+            if incl and disj and not it_bound:
+                it_bound = j
+            if res_ok and not it_res:
+                it_res = j
+            if diff_ok and not it_diff:
+                it_diff = j
+            if incl and disj and res_ok and diff_ok:
+                lam_asc = lam[asc]
+                x = X[:, asc[l - 1]].copy()
+                return (float(lam_asc[l - 1]), x, j, sigma, it_bound, it_res, it_diff)
+        if beta == 0:
+            raise NoConvergence("SI Lanczos reached an invariant subspace before validation")
+        betas.append(beta)
+        V.append(vnext)
+        Vt.append(vtnext)
+    raise NoConvergence("SI Lanczos did not converge")
+
+
+def kth_eig(pencil, k: int | None = None, m_max=20, tau_res=1e-10, tau_diff=1e-10,
+            tau_len=0.0, seed=0, max_iter=500) -> Result:
+    """Alg. 4 over the oracle's sparse LDL^T."""
+    k = pencil.k if k is None else k
+    P = osp.prepare(pencil)
+    A, B = pencil.A(), pencil.B()
+    v0s = pencilgen.start_vectors(pencil.n, seed=seed)
+    # factor of B itself: the pencil (B, 0) at sigma = 0
+    PB = osp.prepare(pencilgen.Pencil(n=pencil.n, rowptr=pencil.rowptr, col=pencil.col,
+                                      a_val=pencil.b_val, b_val=np.zeros_like(pencil.b_val)),
+                     perm=P.perm)
+    Bfac = osp.Factor(PB, 0.0)
+    if Bfac.inertia[0] or Bfac.inertia[1]:
+        raise ValueError("B is not positive definite")
+    nfac = [1]
+    log = []
+
+    def nu_of(s):
+        nfac[0] += 1
+        return osp.nu(P, s)
+
+    sl, su, nl, nu_, s1 = stage1(pencil, k, P, A, B, Bfac, v0s, nu_of, log)
+    sl, su, nl, nu_, s2 = stage2(k, sl, su, nl, nu_, nu_of, log, m_max, tau_len)
+    nfac[0] += 1
+    lam, x, sj, sig, ib, ir, idf = stage3(P, k, sl, su, nl, nu_, A, B, v0s[1], tau_res,
+                                          tau_diff, max_iter)
+    x = x / np.sqrt(np.dot(x, B @ x))
+    i = int(np.argmax(np.abs(x)))
+    if x[i] < 0:
+        x = -x
+    r = A @ x - lam * (B @ x)
+    return Result(lam=lam, x=x, k_validated=k, sigma_lower=sl, sigma_upper=su, nu_lower=nl,
+                  nu_upper=nu_, sigma_si=sig, stage1_steps=s1, bisection_steps=s2, si_steps=sj,
+                  it_bound=ib, it_residual=ir, it_difference=idf,
+                  sigmas=[a for a, _ in log], nus=[b for _, b in log],
+                  rel_residual=float(np.linalg.norm(r) / np.linalg.norm(x)),
+                  n_factorizations=nfac[0])
