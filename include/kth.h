@@ -1,0 +1,169 @@
+/*
+ * kth.h -- C ABI of the MI355X k-th eigenpair library (libkth.so).
+ *
+ * Problem (eq. (1)): A x = lambda B x, A real symmetric, B symmetric positive
+ * definite, n x n sparse; eigenvalues ascending lambda_1 <= ... <= lambda_n; k is
+ * 1-based.  nu(sigma) = #{ i : lambda_i < sigma } (Section 2.1).
+ *
+ * Conventions for every call
+ *   - Every call returns kth_status; nothing throws across the ABI.  On failure a
+ *     message is kept per context (kth_last_error).
+ *   - Matrices: CSR with BOTH triangles stored, 0-based, int64 row pointers,
+ *     int32 column indices strictly increasing within each row, float64 values,
+ *     diagonal entries present.  A and B are given on ONE shared pattern (store
+ *     explicit zeros where one of them has no entry); the pattern must be
+ *     structurally symmetric.
+ *   - Host pointers unless a flag says otherwise.  The library copies what it
+ *     needs; the caller may free its arrays on return.  Output buffers are owned
+ *     by the caller.  Handles are owned by the library and freed by *_destroy.
+ *   - Device memory comes from the context's allocator (hipMalloc unless an
+ *     allocator is injected); work runs on the context's HIP stream.  Calls
+ *     returning host results synchronise that stream.
+ *   - One context per host thread.
+ */
+#ifndef KTH_H
+#define KTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KTH_OK = 0,
+  KTH_EINVAL = 1,      /* invalid argument or malformed pattern                       */
+  KTH_ENOMEM = 2,      /* device or host allocation failed                             */
+  KTH_EDEVICE = 3,     /* HIP runtime error, or no usable gfx950 device                */
+  KTH_ENOTPD = 4,      /* B is not positive definite (its LDL^T has nonpositive pivots) */
+  KTH_ESINGULAR = 5,   /* exactly zero pivot: sigma is an eigenvalue to working precision */
+  KTH_ENOCONV = 6,     /* Lanczos iteration limit reached                              */
+  KTH_ECLUSTER = 7,    /* error bounds never became disjoint (multiple / clustered eigenvalues) */
+  KTH_ESTATE = 8       /* call not valid in the object's current state                  */
+} kth_status;
+
+typedef enum { KTH_FP64 = 0, KTH_FP32_IR = 1 } kth_precision;
+
+typedef struct kth_ctx_s* kth_ctx;
+typedef struct kth_pencil_s* kth_pencil;
+typedef struct kth_factor_s* kth_factor_t;   /* kept numeric factor */
+
+typedef void* (*kth_alloc_fn)(size_t bytes, void* user);
+typedef void (*kth_free_fn)(void* ptr, void* user);
+
+/* pencil flags */
+#define KTH_DEVICE_PTRS    1u  /* value arrays of kth_pencil_set_values are device pointers */
+#define KTH_CHECK_SYMMETRY 2u  /* verify structural symmetry of the pattern (O(nnz log)) */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run on,
+ * or NULL for a stream owned by the context.  alloc/free: device allocator (both
+ * NULL: hipMalloc / hipFree); `user` is passed back to them.
+ * Fails with KTH_EDEVICE if the device is not a gfx950 GPU. */
+kth_status kth_ctx_create(int device, void* hip_stream, kth_alloc_fn alloc, kth_free_fn free_fn,
+                          void* user, kth_ctx* out);
+kth_status kth_ctx_destroy(kth_ctx ctx);
+const char* kth_status_string(kth_status s);
+const char* kth_last_error(kth_ctx ctx);   /* message of the last failing call on ctx ("" if none) */
+
+/* Host-only analysis statistics of a pattern (no device needed): fill-reducing
+ * order, symbolic factorization and the algorithmic flop count of one numeric
+ * LDL^T (sum over columns j of c_j^2 + 2 c_j, c_j = structural nonzeros below the
+ * diagonal of column j of L).  stats[0..15] receives
+ *   n, nnz, n_supervariables, n_supernodes_fundamental, n_supernodes, max_front,
+ *   max_pivot_block, levels, flops, flops_padded, nnz_l, nnz_l_padded,
+ *   front_pool_bytes, factor_bytes, t_order_s, t_symbolic_s.
+ * perm_out (may be NULL): n entries, elimination position -> original index. */
+kth_status kth_analyze(int64_t n, const int64_t* rowptr, const int32_t* col, uint32_t flags,
+                       double* stats, int64_t* perm_out);
+
+/* Create a pencil.  Ordering and symbolic analysis run here on the host
+ * (Section 3.3: they depend on the pattern only and are reused for B and every
+ * shift); values and maps are uploaded.  Pattern/values as described above. */
+kth_status kth_pencil_create(kth_ctx ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
+                             const double* a_val, const double* b_val, uint32_t flags,
+                             kth_pencil* out);
+/* Replace the values (same pattern; the analysis is kept).  flags: KTH_DEVICE_PTRS. */
+kth_status kth_pencil_set_values(kth_pencil p, const double* a_val, const double* b_val,
+                                 uint32_t flags);
+kth_status kth_pencil_destroy(kth_pencil p);
+
+/* nu(sigma) by Sylvester's law of inertia (Section 2.1, Alg. 1'): FP64 multifrontal
+ * LDL^T of A - sigma B (entries formed as fma(-sigma, b, a)) with Bunch-Kaufman
+ * pivots restricted to each front's fully-summed block; nu = number of negative
+ * eigenvalues of D.  nzero (may be NULL) receives the number of exactly zero
+ * pivots; if it is nonzero the call returns KTH_ESINGULAR (nu still written). */
+kth_status kth_inertia(kth_pencil p, double sigma, int64_t* nu, int64_t* nzero);
+/* nu at nsigma shifts in one batched call (multisection).  nu: nsigma entries. */
+kth_status kth_inertia_batch(kth_pencil p, int32_t nsigma, const double* sigmas, int64_t* nu);
+
+/* Numeric factor of A - sigma B kept for solves (the linear systems of Alg. 2 and
+ * Alg. 3).  KTH_FP32_IR factors in FP32 and refines each solve in FP64. */
+kth_status kth_factor(kth_pencil p, double sigma, kth_precision prec, kth_factor_t* out);
+/* Inertia of a kept FP64 factor: counts of negative, zero and positive
+ * eigenvalues of D (neg + zero + pos = n).  KTH_ESTATE for an FP32 factor. */
+kth_status kth_factor_inertia(kth_factor_t f, int64_t* neg, int64_t* zero, int64_t* pos);
+/* Solve (A - sigma B) X = R for nrhs columns (column-major, leading dims >= n).
+ * r and x: host pointers, or device pointers with flags & KTH_DEVICE_PTRS. */
+kth_status kth_solve(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr, double* x,
+                     int64_t ldx, uint32_t flags);
+kth_status kth_factor_destroy(kth_factor_t f);
+
+typedef struct {
+  int64_t m_max;          /* bisection stops at <= m_max eigenvalues in the interval (20)    */
+  double tau_res;         /* relative residual tolerance of Alg. 3 (1e-10)                    */
+  double tau_diff;        /* relative difference tolerance of Alg. 3 (1e-10)                  */
+  double tau_len;         /* bisection also stops below this interval length (0: off)        */
+  int32_t max_lanczos;    /* shift-and-invert Lanczos iteration limit (500)                   */
+  int32_t multisection;   /* shifts per stage-2 round (1: plain bisection)                    */
+  uint64_t seed;          /* seed of the starting vectors, when start_vectors is NULL         */
+  kth_precision si_precision;  /* precision of the shift-and-invert factor                   */
+  const double* start_vectors; /* optional host array [4][n]: row 0 stage 1, row 1 stage 3, rows 2.. restarts */
+  const double* warm_interval; /* optional [2]: sigma_l, sigma_u (skip stages 1-2)             */
+  const int64_t* warm_counts;  /* optional [2]: nu_l, nu_u matching warm_interval              */
+} kth_opts;
+
+typedef struct {
+  int64_t k_validated;    /* index certified by disjoint error bounds (Prop. 3)               */
+  int64_t nu_lower, nu_upper;
+  double sigma_lower, sigma_upper, sigma_si;
+  int32_t stage1_steps, bisection_steps, si_steps, it_bound, it_residual, it_difference;
+  double rel_residual;        /* ||A x - lambda B x||_2 / ||x||_2 (explicit products)         */
+  double rel_residual_normA;  /* ||A x - lambda B x||_2 / (||A||_inf ||x||_2)                  */
+  double eta;                 /* error bound of the returned eigenvalue (Prop. 3)              */
+  double min_pivot_rel;       /* smallest |pivot| / ||A - sigma B||_inf over the factorizations */
+  int64_t n_factorizations;
+  double flops_factor;        /* algorithmic flops of one numeric factorization               */
+  double t_task[7];           /* seconds in tasks (i)-(vii) of Section 4.3                    */
+  double peak_device_bytes;
+  int32_t n_sigmas;           /* shifts whose inertia was computed (stage 1 and 2)            */
+  double sigmas[128];         /* those shifts, in order (first 128)                            */
+  int64_t nus[128];           /* their counts                                                  */
+} kth_info;
+
+void kth_opts_default(kth_opts* o);
+/* The k-th eigenpair by the three-stage algorithm (Alg. 4): Alg. 2 -> Alg. 1' -> Alg. 3.
+ * lambda: the eigenvalue.  x (may be NULL): caller-owned n doubles, B-normalised
+ * (x^T B x = 1) with its largest-|.| entry positive.  info (may be NULL). */
+kth_status kth_eig(kth_pencil p, int64_t k, const kth_opts* opts, double* lambda, double* x,
+                   kth_info* info);
+/* Many pencils in one call (each with its own k). per_pencil: np statuses. */
+kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int64_t* k,
+                         const kth_opts* opts, double* lambda, double* const* x, kth_info* info,
+                         kth_status* per_pencil);
+/* Hellmann-Feynman backward of a simple eigenvalue: for each STORED entry q
+ * (row r, column c): grad_a[q] = g * x_r * x_c and grad_b[q] = -g * lambda * x_r * x_c,
+ * x B-normalised.  x, grad_a, grad_b: host arrays (n, nnz, nnz). */
+kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double g,
+                            double* grad_a, double* grad_b);
+
+/* Diagnostics: one v_mfma_f64_16x16x4 on device 0, zero accumulator; lane l of
+ * the wavefront supplies A[l] and B[l] (64 doubles each) and result register r
+ * of lane l lands in D[4 l + r] (256 doubles).  Host pointers.  Used by the
+ * tests to pin the operand layout the kernels assume. */
+kth_status kth_debug_mfma_probe(const double* A, const double* B, double* D);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KTH_H */

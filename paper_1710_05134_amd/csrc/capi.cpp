@@ -1,0 +1,327 @@
+// extern "C" entry points of libkth.so (declared in include/kth.h).  Each call
+// converts exceptions into a kth_status and keeps the message on its context.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "../../include/kth.h"
+#include "driver.hpp"
+#include "engine.hpp"
+
+using namespace kth;
+
+struct kth_ctx_s {
+  Ctx c;
+};
+struct kth_pencil_s {
+  kth_ctx_s* ctx;
+  Pencil p;
+};
+struct kth_factor_s {
+  kth_pencil_s* pen;
+  NumFactor f;
+};
+
+namespace {
+
+thread_local std::string g_noctx_error;
+
+template <typename F>
+kth_status guarded(Ctx* c, F&& fn) {
+  try {
+    fn();
+    if (c) c->last_error.clear();
+    return KTH_OK;
+  } catch (const Error& e) {
+    if (c) c->last_error = e.what(); else g_noctx_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    if (c) c->last_error = "host allocation failed"; else g_noctx_error = "host allocation failed";
+    return KTH_ENOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->last_error = e.what(); else g_noctx_error = e.what();
+    return KTH_EINVAL;
+  }
+}
+
+void set_device(Ctx& c) { KTH_HIP(hipSetDevice(c.device)); }
+
+}  // namespace
+
+extern "C" {
+
+const char* kth_status_string(kth_status s) {
+  switch (s) {
+    case KTH_OK: return "ok";
+    case KTH_EINVAL: return "invalid argument";
+    case KTH_ENOMEM: return "out of memory";
+    case KTH_EDEVICE: return "device error";
+    case KTH_ENOTPD: return "B is not positive definite";
+    case KTH_ESINGULAR: return "zero pivot (shift is an eigenvalue to working precision)";
+    case KTH_ENOCONV: return "no convergence";
+    case KTH_ECLUSTER: return "error bounds never disjoint (cluster or multiple eigenvalue)";
+    case KTH_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* kth_last_error(kth_ctx ctx) { return ctx ? ctx->c.last_error.c_str() : g_noctx_error.c_str(); }
+
+kth_status kth_ctx_create(int device, void* hip_stream, kth_alloc_fn alloc, kth_free_fn free_fn,
+                          void* user, kth_ctx* out) {
+  if (!out) return KTH_EINVAL;
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    g_noctx_error = "alloc and free must both be given or both be NULL";
+    return KTH_EINVAL;
+  }
+  std::unique_ptr<kth_ctx_s> c(new kth_ctx_s());
+  kth_status st = guarded(nullptr, [&] {
+    int ndev = 0;
+    KTH_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) throw Error(KTH_EDEVICE, "no HIP device " + std::to_string(device));
+    hipDeviceProp_t prop;
+    KTH_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      throw Error(KTH_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    c->c.device = device;
+    KTH_HIP(hipSetDevice(device));
+    if (hip_stream) {
+      c->c.stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      KTH_HIP(hipStreamCreateWithFlags(&c->c.stream, hipStreamNonBlocking));
+      c->c.own_stream = true;
+    }
+    c->c.afn = alloc;
+    c->c.ffn = free_fn;
+    c->c.user = user;
+  });
+  if (st == KTH_OK) *out = c.release();
+  return st;
+}
+
+kth_status kth_ctx_destroy(kth_ctx ctx) {
+  if (!ctx) return KTH_EINVAL;
+  if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
+  delete ctx;
+  return KTH_OK;
+}
+
+kth_status kth_analyze(int64_t n, const int64_t* rowptr, const int32_t* col, uint32_t flags,
+                       double* stats, int64_t* perm_out) {
+  return guarded(nullptr, [&] {
+    if (!rowptr || !col || !stats) throw Error(KTH_EINVAL, "null argument");
+    Pattern pat;
+    pat.n = n;
+    pat.rowptr = rowptr;
+    pat.col = col;
+    std::string msg = check_pattern(pat, (flags & KTH_CHECK_SYMMETRY) != 0);
+    if (!msg.empty()) throw Error(KTH_EINVAL, msg);
+    Symbolic S;
+    AnalysisOpts o;
+    analyze(pat, o, S);
+    stats[0] = (double)n;
+    stats[1] = (double)rowptr[n];
+    stats[2] = (double)S.n_supervars;
+    stats[3] = (double)S.nsup_fundamental;
+    stats[4] = (double)S.nsup;
+    stats[5] = (double)S.max_front;
+    stats[6] = (double)S.max_ns;
+    stats[7] = (double)S.nlevels;
+    stats[8] = S.flops;
+    stats[9] = S.flops_padded;
+    stats[10] = (double)S.nnz_l;
+    stats[11] = (double)S.nnz_l_padded;
+    stats[12] = 8.0 * (double)S.pool_size;
+    stats[13] = 8.0 * (double)S.lptr[S.nsup];
+    stats[14] = S.t_order;
+    stats[15] = S.t_symbolic;
+    if (perm_out) std::memcpy(perm_out, S.perm.data(), sizeof(int64_t) * n);
+  });
+}
+
+kth_status kth_pencil_create(kth_ctx ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
+                             const double* a_val, const double* b_val, uint32_t flags,
+                             kth_pencil* out) {
+  if (!ctx || !out) return KTH_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<kth_pencil_s> p(new kth_pencil_s());
+  p->ctx = ctx;
+  kth_status st = guarded(&ctx->c, [&] {
+    if (!rowptr || !col || !a_val || !b_val) throw Error(KTH_EINVAL, "null argument");
+    if (flags & KTH_DEVICE_PTRS) throw Error(KTH_EINVAL, "kth_pencil_create takes host arrays");
+    set_device(ctx->c);
+    pencil_init(p->p, &ctx->c, n, rowptr, col, a_val, b_val, flags);
+  });
+  if (st == KTH_OK) *out = p.release();
+  return st;
+}
+
+kth_status kth_pencil_set_values(kth_pencil p, const double* a_val, const double* b_val,
+                                 uint32_t flags) {
+  if (!p) return KTH_EINVAL;
+  return guarded(&p->ctx->c, [&] {
+    if (!a_val || !b_val) throw Error(KTH_EINVAL, "null argument");
+    set_device(p->ctx->c);
+    pencil_set_values(p->p, a_val, b_val, (flags & KTH_DEVICE_PTRS) != 0);
+    p->ctx->c.sync();
+  });
+}
+
+kth_status kth_pencil_destroy(kth_pencil p) {
+  if (!p) return KTH_EINVAL;
+  (void)hipSetDevice(p->ctx->c.device);
+  (void)hipStreamSynchronize(p->ctx->c.stream);
+  delete p;
+  return KTH_OK;
+}
+
+kth_status kth_inertia(kth_pencil p, double sigma, int64_t* nu, int64_t* nzero) {
+  if (!p || !nu) return KTH_EINVAL;
+  kth_status st = guarded(&p->ctx->c, [&] {
+    if (!std::isfinite(sigma)) throw Error(KTH_EINVAL, "sigma must be finite");
+    set_device(p->ctx->c);
+    NumFactor& F = *p->p.scratch;
+    factor_enqueue(p->p, F, sigma, false);
+    factor_read_stats(p->p, F);
+    *nu = (int64_t)F.hs.neg;
+    if (nzero) *nzero = (int64_t)F.hs.zero;
+  });
+  if (st == KTH_OK && p->p.scratch->hs.zero > 0) {
+    p->ctx->c.last_error = "zero pivot in LDL^T of A - sigma B";
+    return KTH_ESINGULAR;
+  }
+  return st;
+}
+
+kth_status kth_inertia_batch(kth_pencil p, int32_t nsigma, const double* sigmas, int64_t* nu) {
+  if (!p || !sigmas || !nu || nsigma < 0) return KTH_EINVAL;
+  return guarded(&p->ctx->c, [&] {
+    set_device(p->ctx->c);
+    inertia_batch(p->p, nsigma, sigmas, nu);
+  });
+}
+
+kth_status kth_factor(kth_pencil p, double sigma, kth_precision prec, kth_factor_t* out) {
+  if (!p || !out) return KTH_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<kth_factor_s> f(new kth_factor_s());
+  f->pen = p;
+  kth_status st = guarded(&p->ctx->c, [&] {
+    if (!std::isfinite(sigma)) throw Error(KTH_EINVAL, "sigma must be finite");
+    if (prec != KTH_FP64 && prec != KTH_FP32_IR) throw Error(KTH_EINVAL, "unknown precision");
+    set_device(p->ctx->c);
+    numeric_factor(p->p, f->f, sigma, prec);
+  });
+  if (st == KTH_OK) *out = f.release();
+  return st;
+}
+
+kth_status kth_factor_inertia(kth_factor_t f, int64_t* neg, int64_t* zero, int64_t* pos) {
+  if (!f) return KTH_EINVAL;
+  if (f->f.prec != KTH_FP64 || !f->f.have_stats) {
+    f->pen->ctx->c.last_error = "inertia is only kept for FP64 factors";
+    return KTH_ESTATE;
+  }
+  if (neg) *neg = (int64_t)f->f.hs.neg;
+  if (zero) *zero = (int64_t)f->f.hs.zero;
+  if (pos) *pos = (int64_t)f->f.hs.pos;
+  return KTH_OK;
+}
+
+kth_status kth_solve(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr, double* x,
+                     int64_t ldx, uint32_t flags) {
+  if (!f || !r || !x || nrhs < 0) return KTH_EINVAL;
+  kth_pencil_s* p = f->pen;
+  return guarded(&p->ctx->c, [&] {
+    if (ldr < p->p.n || ldx < p->p.n) throw Error(KTH_EINVAL, "leading dimension smaller than n");
+    set_device(p->ctx->c);
+    solve_many(p->p, f->f, nrhs, r, ldr, x, ldx, (flags & KTH_DEVICE_PTRS) != 0);
+  });
+}
+
+kth_status kth_factor_destroy(kth_factor_t f) {
+  if (!f) return KTH_EINVAL;
+  (void)hipSetDevice(f->pen->ctx->c.device);
+  (void)hipStreamSynchronize(f->pen->ctx->c.stream);
+  delete f;
+  return KTH_OK;
+}
+
+void kth_opts_default(kth_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->m_max = 20;
+  o->tau_res = 1e-10;
+  o->tau_diff = 1e-10;
+  o->tau_len = 0.0;
+  o->max_lanczos = 500;
+  o->multisection = 1;
+  o->seed = 0;
+  o->si_precision = KTH_FP64;
+}
+
+kth_status kth_eig(kth_pencil p, int64_t k, const kth_opts* opts, double* lambda, double* x,
+                   kth_info* info) {
+  if (!p || !lambda) return KTH_EINVAL;
+  kth_opts o;
+  if (opts) o = *opts; else kth_opts_default(&o);
+  kth_info tmp;
+  kth_info* inf = info ? info : &tmp;
+  std::memset(inf, 0, sizeof(*inf));
+  kth_status st = KTH_OK;
+  kth_status g = guarded(&p->ctx->c, [&] {
+    if (k < 1 || k > p->p.n) throw Error(KTH_EINVAL, "k out of range");
+    set_device(p->ctx->c);
+    st = three_stage(p->p, k, o, lambda, x, inf);
+  });
+  return g != KTH_OK ? g : st;
+}
+
+kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int64_t* k,
+                         const kth_opts* opts, double* lambda, double* const* x, kth_info* info,
+                         kth_status* per_pencil) {
+  if (!ctx || np < 0 || (np > 0 && (!p || !k || !lambda || !per_pencil))) return KTH_EINVAL;
+  kth_opts o;
+  if (opts) o = *opts; else kth_opts_default(&o);
+  return guarded(&ctx->c, [&] {
+    set_device(ctx->c);
+    std::vector<Pencil*> ps(np);
+    for (int32_t i = 0; i < np; i++) {
+      if (!p[i] || p[i]->ctx != ctx) throw Error(KTH_EINVAL, "pencil from another context");
+      ps[i] = &p[i]->p;
+    }
+    eig_batch(ctx->c, ps, k, o, lambda, x, info, per_pencil);
+  });
+}
+
+kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double g,
+                            double* grad_a, double* grad_b) {
+  if (!p || !x || !grad_a || !grad_b) return KTH_EINVAL;
+  return guarded(&p->ctx->c, [&] {
+    set_device(p->ctx->c);
+    hf_backward(p->p, lambda, x, g, grad_a, grad_b);
+  });
+}
+
+kth_status kth_debug_mfma_probe(const double* A, const double* B, double* D) {
+  return guarded(nullptr, [&] {
+    double *dA, *dB, *dD;
+    KTH_HIP(hipMalloc(&dA, 64 * sizeof(double)));
+    KTH_HIP(hipMalloc(&dB, 64 * sizeof(double)));
+    KTH_HIP(hipMalloc(&dD, 256 * sizeof(double)));
+    KTH_HIP(hipMemcpy(dA, A, 64 * sizeof(double), hipMemcpyHostToDevice));
+    KTH_HIP(hipMemcpy(dB, B, 64 * sizeof(double), hipMemcpyHostToDevice));
+    launch_mfma_probe(dA, dB, dD, nullptr);
+    KTH_HIP(hipDeviceSynchronize());
+    KTH_HIP(hipMemcpy(D, dD, 256 * sizeof(double), hipMemcpyDeviceToHost));
+    (void)hipFree(dA);
+    (void)hipFree(dB);
+    (void)hipFree(dD);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Device-side data layout shared by the numeric kernels and their host launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kth {
+
+// Tree / front metadata (device pointers, built once per pattern).
+struct FrontMeta {
+  const int64_t* sfirst;  // [nsup+1] first elimination column of each supernode
+  const int64_t* rptr;    // [nsup+1] offsets into rows
+  const int32_t* rows;    // front row lists (elimination indices)
+  const int64_t* lptr;    // [nsup+1] panel offsets (nf*ns, ld nf)
+  const int64_t* uptr;    // [nsup]   update-block offsets in the pool (-1: none)
+  const int64_t* wptr;    // [nsup]   panel-workspace offsets (nf*NB, ld nf; -1: small front)
+  const int64_t* eptr;    // [nsup+1] extend-add map offsets
+  const int32_t* emap;
+  const int64_t* cptr;    // [nsup+1] children
+  const int32_t* clist;
+  const int64_t* acptr;   // [n+1] original entries per elimination column
+  const int64_t* asrc;
+  const int64_t* adst;
+  const int32_t* tilew;   // [nsup] pivot-tile width (ns for fronts factored in one piece)
+};
+
+// Results of one numeric factorization that the host reads back.
+struct FactStats {
+  unsigned long long neg, zero, pos, n2x2;
+  unsigned long long min_d_bits;   // bit pattern of min |eigenvalue of a D block| (>= 0)
+  unsigned long long max_l_bits;   // bit pattern of max |L_ij|
+  unsigned long long pad[2];
+};
+
+// Largest front factored wholly in LDS by one workgroup.
+constexpr int kSmallMaxNf = 128;
+// Pivot-tile width (and panel width) of large fronts.
+constexpr int kNB = 64;
+// Column chunk of the large-front assembly kernel.
+constexpr int kAsmCols = 16;
+// Rows per workgroup of the panel triangular solve.
+constexpr int kTrsmRows = 256;
+// Schur-update output tile.
+constexpr int kTile = 64;
+
+struct Int2 { int32_t a, b; };
+
+// ---- launchers (factor.hip) -----------------------------------------------
+void launch_fill_stats(FactStats* st, hipStream_t s);
+void launch_small_fronts(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t max_nf,
+                         const double* aval, const double* bval, const double* sigma_dev,
+                         double* L, double* U, double* D, double* E, int32_t* tperm,
+                         FactStats* st, hipStream_t s);
+void launch_front_init(const FrontMeta& M, const Int2* tasks, int32_t count, const double* aval,
+                       const double* bval, const double* sigma_dev, double* L, double* U,
+                       hipStream_t s);
+void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t t,
+                        double* L, double* D, double* E, int32_t* tperm, FactStats* st,
+                        hipStream_t s);
+void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, double* L,
+                       double* W, const double* D, const double* E, const int32_t* tperm,
+                       FactStats* st, hipStream_t s);
+void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
+                  int32_t nfronts, int32_t ntiles, int32_t t, double* L, double* U, const double* W,
+                  hipStream_t s);
+void launch_set_scalar(double* p, double v, hipStream_t s);
+// MFMA operand-layout probe (tests only): D = A(16x4) * B(4x16) via one instruction.
+void launch_mfma_probe(const double* A, const double* B, double* D, hipStream_t s);
+
+}  // namespace kth

@@ -1,0 +1,557 @@
+// Three-stage k-th eigenpair algorithm (Alg. 4) on the device engine.
+//
+//   stage 1 (Alg. 2): B-orthonormal Lanczos on (A, B) from a random v1; at step j
+//     the extreme Ritz value theta_1 or theta_j of T_j becomes the shift sigma^(j)
+//     and nu(sigma^(j)) is counted, until two consecutive shifts bracket lambda_k;
+//   stage 2 (Alg. 1'): bisection of [sigma_l, sigma_u) with the inertia count until
+//     it holds at most m_max eigenvalues (or is shorter than tau_len);
+//   stage 3 (Alg. 3): shift-and-invert Lanczos at the midpoint with full
+//     reorthogonalisation; from step m on, Ritz pairs (eq. (13), eq. (15)),
+//     error bounds (Prop. 3), inclusion / disjointness, residual (eq. (res2)) and
+//     relative-difference tests; the l = k - nu_l -th pair of the interval is
+//     returned with its index validated.
+// Readings of points the paper leaves open are the same as the oracle's:
+// starting vectors (caller-provided rows, else the library's own generator),
+// CGS2 in both Lanczos processes, V = B^{-1} V~ kept with V~ = B V, the m pairs of
+// largest |theta~| (ties: larger theta~), closed bounds inside [sigma_l, sigma_u),
+// relative differences matched in ascending order after sign alignment.
+#include "driver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "blas.hpp"
+
+namespace kth {
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// splitmix64 + Box-Muller: the library's own N(0,1) start vectors when the caller gives none.
+void gen_start(int64_t n, uint64_t seed, int row, std::vector<double>& out) {
+  out.resize(n);
+  uint64_t s = seed * 0x9E3779B97F4A7C15ull + 0xD1B54A32D192ED03ull * (uint64_t)(row + 1);
+  auto next = [&]() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  for (int64_t i = 0; i < n; i += 2) {
+    double u1 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    double u2 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    double r = std::sqrt(-2.0 * std::log(u1)), t = 6.283185307179586 * u2;
+    out[i] = r * std::cos(t);
+    if (i + 1 < n) out[i + 1] = r * std::sin(t);
+  }
+}
+
+struct Work {
+  Ctx* c = nullptr;
+  int64_t n = 0;
+  int cap = 0;
+  DBuf<double> V, Vt;           // basis and its B-image (n x cap each)
+  DBuf<double> w, Bw, ya, yb;   // n-vectors
+  DBuf<double> partial, h, h2, sc;
+  DBuf<double> alpha_d, beta_d, theta_d, Y_d, twork;
+  DBuf<double> C_d, cu_d, f_d, X, Xn, Prev, Dif;
+  DBuf<int32_t> perm_d;
+  int tcap = 0, mcap = 0;
+
+  void init(Ctx* ctx, int64_t nn) {
+    c = ctx;
+    n = nn;
+    w.alloc(c, n);
+    Bw.alloc(c, n);
+    ya.alloc(c, n);
+    yb.alloc(c, n);
+    sc.alloc(c, 4096);
+    ensure_cols(64);
+  }
+  void ensure_cols(int need) {
+    if (need <= cap) return;
+    int nc = std::max(need, cap * 2);
+    DBuf<double> V2, Vt2;
+    V2.alloc(c, (size_t)n * nc);
+    Vt2.alloc(c, (size_t)n * nc);
+    if (cap) {
+      KTH_HIP(hipMemcpyAsync(V2.get(), V.get(), sizeof(double) * n * cap, hipMemcpyDeviceToDevice, c->stream));
+      KTH_HIP(hipMemcpyAsync(Vt2.get(), Vt.get(), sizeof(double) * n * cap, hipMemcpyDeviceToDevice, c->stream));
+    }
+    V.swap(V2);
+    Vt.swap(Vt2);
+    cap = nc;
+    partial.alloc(c, (size_t)multidot_blocks(n) * (cap + 72));
+    h.alloc(c, cap + 8);
+    h2.alloc(c, cap + 8);
+  }
+  void ensure_tri(int j) {
+    if (j <= tcap) return;
+    int nc = std::max(j, 2 * tcap);
+    alpha_d.alloc(c, nc);
+    beta_d.alloc(c, nc);
+    theta_d.alloc(c, nc);
+    Y_d.alloc(c, (size_t)nc * nc);
+    twork.alloc(c, (size_t)5 * nc * nc);
+    tcap = nc;
+  }
+  void ensure_m(int m, int j) {
+    if (m > mcap) {
+      int nm = std::max(m, 8);
+      X.alloc(c, (size_t)n * nm);
+      Xn.alloc(c, (size_t)n * nm);
+      Prev.alloc(c, (size_t)n * nm);
+      Dif.alloc(c, (size_t)n * nm);
+      f_d.alloc(c, nm);
+      cu_d.alloc(c, nm);
+      perm_d.alloc(c, nm);
+      mcap = nm;
+    }
+    C_d.alloc(c, (size_t)std::max(j, 1) * std::max(m, 1));
+  }
+  double* v(int col) { return V.get() + (size_t)n * col; }
+  double* vt(int col) { return Vt.get() + (size_t)n * col; }
+};
+
+template <typename T>
+void d2h(Ctx* c, T* host, const T* dev, size_t count) {
+  KTH_HIP(hipMemcpyAsync(host, dev, sizeof(T) * count, hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+}
+template <typename T>
+void h2d(Ctx* c, T* dev, const T* host, size_t count) {
+  KTH_HIP(hipMemcpyAsync(dev, host, sizeof(T) * count, hipMemcpyHostToDevice, c->stream));
+}
+
+double dot_dev(Work& W, const double* a, const double* b) {
+  multidot(W.n, 1, a, W.n, b, W.partial.get(), W.sc.get(), 1.0, W.c->stream);
+  double r;
+  d2h(W.c, &r, W.sc.get(), 1);
+  return r;
+}
+
+// nu(sigma) with the pencil's scratch factor; returns neg, sets zero count
+int64_t count_nu(Pencil& P, double sigma, int64_t* zero, double* mind) {
+  NumFactor& F = *P.scratch;
+  factor_enqueue(P, F, sigma, false);
+  factor_read_stats(P, F);
+  if (zero) *zero = (int64_t)F.hs.zero;
+  if (mind) {
+    double md;
+    unsigned long long b = F.hs.min_d_bits;
+    std::memcpy(&md, &b, sizeof(md));
+    *mind = md;
+  }
+  return (int64_t)F.hs.neg;
+}
+
+struct Shifts {
+  std::vector<double> s;
+  std::vector<int64_t> nu;
+  double min_pivot_rel = INFINITY;
+};
+
+// nu at sigma; a shift that hits an exact zero pivot moves by `nudge` (repeatedly).
+int64_t nu_checked(Pencil& P, double& sigma, double nudge, Shifts& log, int64_t* nfac) {
+  for (int attempt = 0; attempt < 8; attempt++) {
+    int64_t zero = 0;
+    double md = 0;
+    int64_t nu = count_nu(P, sigma, &zero, &md);
+    (*nfac)++;
+    double scale = P.normA_inf + std::fabs(sigma) * P.normB_inf;
+    if (scale > 0) log.min_pivot_rel = std::min(log.min_pivot_rel, md / scale);
+    if (zero == 0) {
+      log.s.push_back(sigma);
+      log.nu.push_back(nu);
+      return nu;
+    }
+    sigma += nudge * (attempt + 1);
+  }
+  throw Error(KTH_ESINGULAR, "repeated zero pivots near sigma");
+}
+
+}  // namespace
+
+void numeric_factor(Pencil& P, NumFactor& F, double sigma, kth_precision prec) {
+  if (prec != KTH_FP64) throw Error(KTH_EINVAL, "only FP64 factors are available in this build");
+  factor_alloc(P, F);
+  F.prec = prec;
+  factor_enqueue(P, F, sigma, false);
+  factor_read_stats(P, F);
+}
+
+void solve_many(Pencil& P, NumFactor& F, int32_t nrhs, const double* r, int64_t ldr, double* x,
+                int64_t ldx, bool device_ptrs) {
+  Ctx* c = P.ctx;
+  DBuf<double> rb, xb;
+  if (!device_ptrs) {
+    rb.alloc(c, P.n);
+    xb.alloc(c, P.n);
+  }
+  for (int32_t q = 0; q < nrhs; q++) {
+    const double* rq = r + (size_t)q * ldr;
+    double* xq = x + (size_t)q * ldx;
+    if (device_ptrs) {
+      solve_enqueue_f(P, F, rq, xq);
+    } else {
+      h2d(c, rb.get(), rq, P.n);
+      solve_enqueue_f(P, F, rb.get(), xb.get());
+      d2h(c, xq, xb.get(), P.n);
+    }
+  }
+  c->sync();
+}
+
+void inertia_batch(Pencil& P, int32_t nsigma, const double* sigmas, int64_t* nu) {
+  for (int32_t i = 0; i < nsigma; i++) {
+    if (!std::isfinite(sigmas[i])) throw Error(KTH_EINVAL, "sigma must be finite");
+    nu[i] = count_nu(P, sigmas[i], nullptr, nullptr);
+  }
+}
+
+kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, double* xout,
+                       kth_info* info) {
+  Ctx* c = P.ctx;
+  hipStream_t st = c->stream;
+  const int64_t n = P.n;
+  const double nA = P.normA_inf;
+  Work W;
+  W.init(c, n);
+  Shifts log;
+  int64_t nfac = 0;
+  double t_task[7] = {P.S.t_order + P.S.t_symbolic, 0, 0, 0, 0, 0, 0};
+  auto start_vec = [&](int row, std::vector<double>& v) {
+    if (o.start_vectors) v.assign(o.start_vectors + (size_t)row * n, o.start_vectors + (size_t)(row + 1) * n);
+    else gen_start(n, o.seed, row, v);
+  };
+  std::vector<double> hv;
+
+  // ---- task (ii): factor of B (its inertia must be (0, 0, n)) ----
+  double t0 = now_s();
+  NumFactor FB;
+  factor_alloc(P, FB);
+  factor_enqueue(P, FB, 0.0, true);
+  factor_read_stats(P, FB);
+  nfac++;
+  if (FB.hs.neg != 0 || FB.hs.zero != 0) throw Error(KTH_ENOTPD, "B is not positive definite");
+  t_task[1] = now_s() - t0;
+
+  double sl, su;
+  int64_t nl, nu_;
+  int s1 = 0, s2 = 0;
+  if (o.warm_interval && o.warm_counts) {
+    sl = o.warm_interval[0];
+    su = o.warm_interval[1];
+    nl = o.warm_counts[0];
+    nu_ = o.warm_counts[1];
+    if (!(sl < su) || !(nl < k && k <= nu_)) throw Error(KTH_EINVAL, "warm interval does not bracket k");
+  } else {
+    // ---- stage 1: Alg. 2 ----
+    int restart = 0;
+    bool done = false;
+    while (!done) {
+      start_vec(restart == 0 ? 0 : 1 + restart, hv);
+      h2d(c, W.v(0), hv.data(), n);
+      spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.v(0), nullptr, W.vt(0), st);
+      double nb = std::sqrt(dot_dev(W, W.v(0), W.vt(0)));
+      scale_copy(n, 1.0 / nb, W.v(0), W.v(0), st);
+      scale_copy(n, 1.0 / nb, W.vt(0), W.vt(0), st);
+      std::vector<double> al, be;
+      int64_t nu_prev = 0;
+      double sig_prev = 0;
+      for (int j = 1;; j++) {
+        W.ensure_cols(j + 1);
+        // A v_j, alpha_j, w = B^{-1} A v_j
+        spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.v(j - 1), W.ya.get(), nullptr, st);
+        al.push_back(dot_dev(W, W.v(j - 1), W.ya.get()));
+        solve_enqueue_f(P, FB, W.ya.get(), W.w.get());
+        KTH_HIP(hipMemcpyAsync(W.Bw.get(), W.ya.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        for (int pass = 0; pass < 2; pass++) {   // CGS2 in the B inner product: h = V^T (B w)
+          multidot(n, j, W.V.get(), n, W.Bw.get(), W.partial.get(), W.h.get(), 1.0, st);
+          multiaxpy(n, j, W.V.get(), n, W.h.get(), W.w.get(), W.Vt.get(), W.Bw.get(), st);
+        }
+        // Ritz values of T_j (task iii)
+        double tr0 = now_s();
+        W.ensure_tri(j);
+        h2d(c, W.alpha_d.get(), al.data(), j);
+        if (j > 1) h2d(c, W.beta_d.get(), be.data(), j - 1);
+        tridiag_eig(j, W.alpha_d.get(), W.beta_d.get(), W.theta_d.get(), W.Y_d.get(), W.twork.get(), st);
+        std::vector<double> th(j);
+        d2h(c, th.data(), W.theta_d.get(), j);
+        t_task[2] += now_s() - tr0;
+        double sig = (k <= nu_prev) ? th[0] : th[j - 1];
+        double tf = now_s();
+        int64_t nu = nu_checked(P, sig, 1e-12 * std::max(nA, 1.0), log, &nfac);
+        t_task[3] += now_s() - tf;
+        s1 = j;
+        if (j != 1 && ((nu < k && k <= nu_prev) || (nu_prev < k && k <= nu))) {
+          sl = std::min(sig_prev, sig);
+          su = std::max(sig_prev, sig);
+          nl = std::min(nu_prev, nu);
+          nu_ = std::max(nu_prev, nu);
+          done = true;
+          break;
+        }
+        sig_prev = sig;
+        nu_prev = nu;
+        double beta = std::sqrt(std::max(dot_dev(W, W.w.get(), W.Bw.get()), 0.0));
+        if (!(beta > 1e-14 * std::max(1.0, std::fabs(al.back())))) {
+          if (++restart > 2) throw Error(KTH_ENOCONV, "stage-1 Lanczos broke down repeatedly");
+          break;   // restart with the next seeded vector
+        }
+        be.push_back(beta);
+        scale_copy(n, 1.0 / beta, W.w.get(), W.v(j), st);
+        scale_copy(n, 1.0 / beta, W.Bw.get(), W.vt(j), st);
+        if (j > n + 1) throw Error(KTH_ENOCONV, "stage 1 exceeded n steps");
+      }
+    }
+    // ---- stage 2: Alg. 1' (repeat-until: at least one bisection step) ----
+    double tb = now_s();
+    const int ms = std::max(1, o.multisection);
+    while (true) {
+      if (ms == 1) {
+        double sig = 0.5 * (sl + su);
+        int64_t nu = nu_checked(P, sig, 1e-3 * (su - sl), log, &nfac);
+        s2++;
+        if (k <= nu) { su = sig; nu_ = nu; } else { sl = sig; nl = nu; }
+      } else {
+        std::vector<double> sg(ms);
+        std::vector<int64_t> cnt(ms);
+        for (int i = 0; i < ms; i++) sg[i] = sl + (su - sl) * (double)(i + 1) / (double)(ms + 1);
+        for (int i = 0; i < ms; i++) cnt[i] = nu_checked(P, sg[i], 1e-3 * (su - sl) / (ms + 1), log, &nfac);
+        s2++;
+        double nsl = sl, nsu = su;
+        int64_t nnl = nl, nnu = nu_;
+        for (int i = 0; i < ms; i++) {
+          if (k <= cnt[i]) { nsu = sg[i]; nnu = cnt[i]; break; }
+          nsl = sg[i];
+          nnl = cnt[i];
+        }
+        sl = nsl; su = nsu; nl = nnl; nu_ = nnu;
+      }
+      if (nu_ - nl <= o.m_max) break;
+      if (o.tau_len > 0 && (su - sl) < o.tau_len) break;
+      if (s2 > 200) throw Error(KTH_ECLUSTER, "bisection did not isolate a small interval");
+    }
+    t_task[4] = now_s() - tb;
+  }
+
+  // ---- stage 3: Alg. 3 ----
+  const int64_t l = k - nl;
+  const int m = (int)(nu_ - nl);
+  double sigma = 0.5 * (sl + su);
+  double tsi = now_s();
+  NumFactor FS;
+  factor_alloc(P, FS);
+  for (int attempt = 0;; attempt++) {
+    factor_enqueue(P, FS, sigma, false);
+    factor_read_stats(P, FS);
+    nfac++;
+    if (FS.hs.zero == 0) break;
+    if (attempt > 6) throw Error(KTH_ESINGULAR, "shift-and-invert factor keeps hitting zero pivots");
+    sigma += 1e-3 * (su - sl);
+  }
+  if ((int64_t)FS.hs.neg < nl || (int64_t)FS.hs.neg > nu_)
+    throw Error(KTH_EDEVICE, "inertia at the interval midpoint is outside [nu_l, nu_u]");
+  t_task[5] = now_s() - tsi;
+  double t3 = now_s();
+  start_vec(1, hv);
+  h2d(c, W.v(0), hv.data(), n);
+  spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.v(0), nullptr, W.vt(0), st);
+  {
+    double nb = std::sqrt(dot_dev(W, W.v(0), W.vt(0)));
+    scale_copy(n, 1.0 / nb, W.v(0), W.v(0), st);
+    scale_copy(n, 1.0 / nb, W.vt(0), W.vt(0), st);
+  }
+  std::vector<double> al, be;
+  bool have_prev = false;
+  int it_bound = 0, it_res = 0, it_diff = 0, j_done = 0;
+  bool ever_incl_not_disj = false;
+  kth_status result = KTH_ENOCONV;
+  double lam_out = 0, eta_out = 0;
+  for (int j = 1; j <= o.max_lanczos; j++) {
+    W.ensure_cols(j + 1);
+    // w = (A - sigma B)^{-1} v~_j, Bw = B w
+    solve_enqueue_f(P, FS, W.vt(j - 1), W.w.get());
+    spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.w.get(), nullptr, W.Bw.get(), st);
+    // CGS2 in the B inner product: h = V~^T w = V^T B w
+    multidot(n, j, W.Vt.get(), n, W.w.get(), W.partial.get(), W.h.get(), 1.0, st);
+    multiaxpy(n, j, W.V.get(), n, W.h.get(), W.w.get(), W.Vt.get(), W.Bw.get(), st);
+    multidot(n, j, W.Vt.get(), n, W.w.get(), W.partial.get(), W.h2.get(), 1.0, st);
+    multiaxpy(n, j, W.V.get(), n, W.h2.get(), W.w.get(), W.Vt.get(), W.Bw.get(), st);
+    double alpha;
+    d2h(c, &alpha, W.h.get() + (j - 1), 1);
+    al.push_back(alpha);
+    double beta = std::sqrt(std::max(dot_dev(W, W.w.get(), W.Bw.get()), 0.0));
+    if (beta > 0) {
+      scale_copy(n, 1.0 / beta, W.w.get(), W.v(j), st);
+      scale_copy(n, 1.0 / beta, W.Bw.get(), W.vt(j), st);
+    } else {
+      KTH_HIP(hipMemsetAsync(W.v(j), 0, sizeof(double) * n, st));
+      KTH_HIP(hipMemsetAsync(W.vt(j), 0, sizeof(double) * n, st));
+    }
+    j_done = j;
+    if (j >= m) {
+      W.ensure_tri(j);
+      h2d(c, W.alpha_d.get(), al.data(), j);
+      if (j > 1) h2d(c, W.beta_d.get(), be.data(), j - 1);
+      tridiag_eig(j, W.alpha_d.get(), W.beta_d.get(), W.theta_d.get(), W.Y_d.get(), W.twork.get(), st);
+      std::vector<double> th(j), Y((size_t)j * j);
+      d2h(c, th.data(), W.theta_d.get(), j);
+      d2h(c, Y.data(), W.Y_d.get(), (size_t)j * j);
+      std::vector<int> ord(j);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        if (std::fabs(th[a]) != std::fabs(th[b])) return std::fabs(th[a]) > std::fabs(th[b]);
+        return th[a] > th[b];
+      });
+      ord.resize(m);
+      std::vector<double> lam(m), s(m), eta(m), C((size_t)j * m), cu(m);
+      for (int q = 0; q < m; q++) {
+        const int i = ord[q];
+        const double yl = Y[(size_t)i * j + (j - 1)];
+        lam[q] = sigma + 1.0 / th[i];
+        s[q] = beta * yl / th[i];
+        eta[q] = (1.0 / std::fabs(th[i])) * std::fabs(s[q]) / std::sqrt(1.0 + s[q] * s[q]);
+        for (int cc = 0; cc < j; cc++) C[(size_t)q * j + cc] = th[i] * Y[(size_t)i * j + cc];
+        cu[q] = beta * yl;
+      }
+      bool incl = true;
+      for (int q = 0; q < m; q++) incl = incl && (lam[q] - eta[q] >= sl) && (lam[q] + eta[q] < su);
+      std::vector<int> asc(m);
+      std::iota(asc.begin(), asc.end(), 0);
+      std::stable_sort(asc.begin(), asc.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+      bool disj = true;
+      for (int q = 0; q + 1 < m; q++)
+        disj = disj && (lam[asc[q]] + eta[asc[q]] < lam[asc[q + 1]] - eta[asc[q + 1]]);
+      if (incl && !disj) ever_incl_not_disj = true;
+      // Ritz vectors x_{i,2} (eq. (15)), their norms, residual test (eq. (res2))
+      W.ensure_m(m, j);
+      h2d(c, W.C_d.get(), C.data(), C.size());
+      h2d(c, W.cu_d.get(), cu.data(), m);
+      ritz_vectors(n, j, m, W.V.get(), n, W.C_d.get(), W.v(j), W.cu_d.get(), W.X.get(), n, st);
+      std::vector<double> xn2(m);
+      multidot2(n, m, W.X.get(), n, W.X.get(), n, W.partial.get(), W.sc.get(), 1.0, st);
+      d2h(c, xn2.data(), W.sc.get(), m);
+      double vtn = std::sqrt(dot_dev(W, W.vt(j), W.vt(j)));
+      bool res_ok = true;
+      for (int q = 0; q < m; q++) res_ok = res_ok && (std::fabs(s[q]) * vtn / std::sqrt(xn2[q]) < o.tau_res);
+      // normalised, ascending copies and the relative difference to the previous step
+      std::vector<int32_t> pa(m);
+      std::vector<double> fa(m);
+      for (int q = 0; q < m; q++) { pa[q] = asc[q]; fa[q] = 1.0 / std::sqrt(xn2[asc[q]]); }
+      h2d(c, W.perm_d.get(), pa.data(), m);
+      h2d(c, W.f_d.get(), fa.data(), m);
+      gather_cols(n, m, W.X.get(), n, W.perm_d.get(), W.f_d.get(), W.Xn.get(), n, st);
+      bool diff_ok = false;
+      if (have_prev) {
+        std::vector<double> dd(m), sg(m);
+        multidot2(n, m, W.Xn.get(), n, W.Prev.get(), n, W.partial.get(), W.sc.get(), 1.0, st);
+        d2h(c, dd.data(), W.sc.get(), m);
+        for (int q = 0; q < m; q++) sg[q] = dd[q] < 0 ? -1.0 : 1.0;
+        h2d(c, W.f_d.get(), sg.data(), m);
+        diff_cols(n, m, W.Xn.get(), n, W.f_d.get(), W.Prev.get(), n, W.Dif.get(), n, st);
+        multidot2(n, m, W.Dif.get(), n, W.Dif.get(), n, W.partial.get(), W.sc.get(), 1.0, st);
+        d2h(c, dd.data(), W.sc.get(), m);
+        diff_ok = true;
+        for (int q = 0; q < m; q++) diff_ok = diff_ok && (std::sqrt(dd[q]) < o.tau_diff);
+      }
+      W.Xn.swap(W.Prev);
+      have_prev = true;
+      if (incl && disj && !it_bound) it_bound = j;
+      if (res_ok && !it_res) it_res = j;
+      if (diff_ok && !it_diff) it_diff = j;
+      if (incl && disj && res_ok && diff_ok) {
+        const int q = asc[l - 1];
+        lam_out = lam[q];
+        eta_out = eta[q];
+        // x = x_{l,2}, B-normalised, largest-|.| entry positive
+        double* xq = W.X.get() + (size_t)n * q;
+        spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), xq, W.ya.get(), W.yb.get(), st);
+        double xbx = dot_dev(W, xq, W.yb.get());
+        double xx = dot_dev(W, xq, xq);
+        residual(n, lam_out, W.ya.get(), W.yb.get(), W.w.get(), st);
+        double rr = dot_dev(W, W.w.get(), W.w.get());
+        const double scale = 1.0 / std::sqrt(xbx);
+        std::vector<double> hx(n);
+        d2h(c, hx.data(), xq, n);
+        int64_t imax = 0;
+        for (int64_t i = 1; i < n; i++) if (std::fabs(hx[i]) > std::fabs(hx[imax])) imax = i;
+        const double sgn = hx[imax] < 0 ? -1.0 : 1.0;
+        if (xout) for (int64_t i = 0; i < n; i++) xout[i] = sgn * scale * hx[i];
+        info->rel_residual = std::sqrt(rr) / std::sqrt(xx);
+        info->rel_residual_normA = info->rel_residual / (nA > 0 ? nA : 1.0);
+        result = KTH_OK;
+        break;
+      }
+    }
+    if (beta == 0) break;
+    be.push_back(beta);
+  }
+  t_task[6] = now_s() - t3;
+  if (result != KTH_OK && ever_incl_not_disj) result = KTH_ECLUSTER;
+  *lambda = lam_out;
+  info->k_validated = result == KTH_OK ? k : 0;
+  info->nu_lower = nl;
+  info->nu_upper = nu_;
+  info->sigma_lower = sl;
+  info->sigma_upper = su;
+  info->sigma_si = sigma;
+  info->stage1_steps = s1;
+  info->bisection_steps = s2;
+  info->si_steps = j_done;
+  info->it_bound = it_bound;
+  info->it_residual = it_res;
+  info->it_difference = it_diff;
+  info->eta = eta_out;
+  info->min_pivot_rel = log.min_pivot_rel;
+  info->n_factorizations = nfac;
+  info->flops_factor = P.S.flops;
+  for (int q = 0; q < 7; q++) info->t_task[q] = t_task[q];
+  info->peak_device_bytes = c->peak_bytes;
+  info->n_sigmas = (int32_t)std::min<size_t>(log.s.size(), 128);
+  for (int q = 0; q < info->n_sigmas; q++) {
+    info->sigmas[q] = log.s[q];
+    info->nus[q] = log.nu[q];
+  }
+  if (result != KTH_OK) {
+    c->last_error = result == KTH_ECLUSTER ? "error bounds never became disjoint"
+                                           : "shift-and-invert Lanczos did not converge";
+  }
+  return result;
+}
+
+void eig_batch(Ctx& c, const std::vector<Pencil*>& ps, const int64_t* k, const kth_opts& o,
+               double* lambda, double* const* x, kth_info* info, kth_status* per) {
+  for (size_t i = 0; i < ps.size(); i++) {
+    kth_info tmp;
+    kth_info* inf = info ? info + i : &tmp;
+    std::memset(inf, 0, sizeof(*inf));
+    try {
+      if (k[i] < 1 || k[i] > ps[i]->n) throw Error(KTH_EINVAL, "k out of range");
+      per[i] = three_stage(*ps[i], k[i], o, lambda + i, x ? x[i] : nullptr, inf);
+    } catch (const Error& e) {
+      per[i] = e.status;
+      c.last_error = e.what();
+    }
+  }
+}
+
+void hf_backward(Pencil& P, double lambda, const double* x, double g, double* ga, double* gb) {
+  Ctx* c = P.ctx;
+  DBuf<double> xd, gad, gbd;
+  xd.upload(c, x, P.n);
+  gad.alloc(c, P.nnz);
+  gbd.alloc(c, P.nnz);
+  hf_gradient(P.n, P.rowptr.get(), P.col.get(), xd.get(), g, lambda, gad.get(), gbd.get(), c->stream);
+  d2h(c, ga, gad.get(), P.nnz);
+  d2h(c, gb, gbd.get(), P.nnz);
+}
+
+}  // namespace kth

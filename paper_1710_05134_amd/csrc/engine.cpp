@@ -1,0 +1,273 @@
+// Host orchestration: allocation, pattern analysis -> device schedule, and the
+// level-by-level launch sequence of the numeric factorization.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace kth {
+
+void* Ctx::alloc(size_t bytes) {
+  void* p = nullptr;
+  if (afn) {
+    p = afn(bytes, user);
+    if (!p) throw Error(KTH_ENOMEM, "device allocator returned NULL for " + std::to_string(bytes) + " bytes");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess || !p)
+      throw Error(KTH_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+  }
+  cur_bytes += (double)bytes;
+  peak_bytes = std::max(peak_bytes, cur_bytes);
+  return p;
+}
+
+void Ctx::release(void* p, size_t bytes) {
+  if (!p) return;
+  if (ffn) ffn(p, user);
+  else (void)hipFree(p);
+  cur_bytes -= (double)bytes;
+}
+
+void Ctx::sync() { KTH_HIP(hipStreamSynchronize(stream)); }
+
+static double csr_norm_inf(int64_t n, const int64_t* rp, const double* v) {
+  double m = 0;
+  for (int64_t i = 0; i < n; i++) {
+    double s = 0;
+    for (int64_t q = rp[i]; q < rp[i + 1]; q++) s += std::fabs(v[q]);
+    m = std::max(m, s);
+  }
+  return m;
+}
+
+static void build_schedule(Pencil& P) {
+  const Symbolic& S = P.S;
+  std::vector<int32_t> sched;
+  auto align2 = [&]() { if (sched.size() & 1) sched.push_back(0); };
+  std::vector<std::vector<int32_t>> bylevel(S.nlevels);
+  for (int64_t s = 0; s < S.nsup; s++) bylevel[S.level[s]].push_back((int32_t)s);
+  std::vector<int64_t> wptr(S.nsup, -1);
+  std::vector<int32_t> tilew(S.nsup, 0);
+  P.wsize = 1;
+  P.levels.assign(S.nlevels, LevelPlan());
+  for (int64_t L = 0; L < S.nlevels; L++) {
+    LevelPlan& lp = P.levels[L];
+    std::vector<int32_t> small, large;
+    for (int32_t s : bylevel[L]) (S.nf(s) <= kSmallMaxNf ? small : large).push_back(s);
+    lp.small_off = (int32_t)sched.size();
+    lp.small_cnt = (int32_t)small.size();
+    for (int32_t s : small) {
+      sched.push_back(s);
+      lp.small_maxnf = std::max<int32_t>(lp.small_maxnf, (int32_t)S.nf(s));
+      tilew[s] = (int32_t)std::max<int64_t>(S.ns(s), 1);
+    }
+    std::stable_sort(large.begin(), large.end(), [&](int32_t a, int32_t b) { return S.ns(a) > S.ns(b); });
+    lp.large_off = (int32_t)sched.size();
+    lp.large_cnt = (int32_t)large.size();
+    int64_t woff = 0;
+    for (int32_t s : large) {
+      sched.push_back(s);
+      tilew[s] = kNB;
+      wptr[s] = woff;
+      woff += S.nf(s) * kNB;
+    }
+    P.wsize = std::max(P.wsize, woff);
+    align2();
+    lp.init_off = (int32_t)sched.size();
+    for (int32_t s : large)
+      for (int64_t c0 = 0; c0 < S.nf(s); c0 += kAsmCols) { sched.push_back(s); sched.push_back((int32_t)c0); }
+    lp.init_cnt = (int32_t)((sched.size() - lp.init_off) / 2);
+    int64_t tmax = 0;
+    for (int32_t s : large) tmax = std::max<int64_t>(tmax, (S.ns(s) + kNB - 1) / kNB);
+    for (int64_t t = 0; t < tmax; t++) {
+      StepPlan sp{};
+      sp.t = (int32_t)t;
+      int32_t act = 0;
+      while (act < (int32_t)large.size() && S.ns(large[act]) > t * kNB) act++;
+      sp.nfronts = act;
+      align2();
+      sp.trsm_off = (int32_t)sched.size();
+      for (int32_t q = 0; q < act; q++) {
+        int32_t s = large[q];
+        int64_t ns = S.ns(s), nf = S.nf(s);
+        int64_t k0 = t * kNB, kb = std::min<int64_t>(kNB, ns - k0);
+        for (int64_t r = k0 + kb; r < nf; r += kTrsmRows) { sched.push_back(s); sched.push_back((int32_t)r); }
+      }
+      sp.trsm_cnt = (int32_t)((sched.size() - sp.trsm_off) / 2);
+      sp.prefix_off = (int32_t)sched.size();
+      int64_t tot = 0;
+      for (int32_t q = 0; q < act; q++) {
+        sched.push_back((int32_t)tot);
+        int32_t s = large[q];
+        int64_t ns = S.ns(s), nf = S.nf(s);
+        int64_t k0 = t * kNB, kb = std::min<int64_t>(kNB, ns - k0), r0 = k0 + kb;
+        int64_t nc1 = r0 < ns ? (ns - r0 + kTile - 1) / kTile : 0;
+        int64_t nc2 = (nf - ns + kTile - 1) / kTile;
+        int64_t T = nc1 + nc2;
+        tot += T * (T + 1) / 2;
+      }
+      sched.push_back((int32_t)tot);
+      if (tot > INT32_MAX) throw Error(KTH_EINVAL, "front too large for the tile schedule");
+      sp.ntiles = (int32_t)tot;
+      lp.steps.push_back(sp);
+    }
+  }
+  // solve plan: all fronts by level
+  std::vector<int32_t> sfronts;
+  P.splan.level_off.clear();
+  P.splan.level_cnt.clear();
+  for (int64_t L = 0; L < S.nlevels; L++) {
+    P.splan.level_off.push_back((int32_t)(sched.size() + sfronts.size()));
+    P.splan.level_cnt.push_back((int32_t)bylevel[L].size());
+    sfronts.insert(sfronts.end(), bylevel[L].begin(), bylevel[L].end());
+  }
+  sched.insert(sched.end(), sfronts.begin(), sfronts.end());
+  Ctx* c = P.ctx;
+  P.d_sched.upload(c, sched);
+  P.d_wptr.upload(c, wptr);
+  P.d_tilew.upload(c, tilew);
+  P.splan.fronts = P.d_sched.get();
+}
+
+void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
+                 const double* a, const double* b, uint32_t flags) {
+  P.ctx = ctx;
+  P.n = n;
+  Pattern pat;
+  pat.n = n;
+  pat.rowptr = rowptr;
+  pat.col = col;
+  std::string msg = check_pattern(pat, (flags & KTH_CHECK_SYMMETRY) != 0);
+  if (!msg.empty()) throw Error(KTH_EINVAL, msg);
+  P.nnz = rowptr[n];
+  P.h_rowptr.assign(rowptr, rowptr + n + 1);
+  P.h_col.assign(col, col + P.nnz);
+  pat.rowptr = P.h_rowptr.data();
+  pat.col = P.h_col.data();
+  AnalysisOpts o;
+  analyze(pat, o, P.S);
+  const Symbolic& S = P.S;
+  P.rowptr.upload(ctx, P.h_rowptr);
+  P.col.upload(ctx, P.h_col);
+  P.aval.alloc(ctx, P.nnz);
+  P.bval.alloc(ctx, P.nnz);
+  P.zeros.alloc(ctx, P.nnz);
+  KTH_HIP(hipMemsetAsync(P.zeros.get(), 0, P.nnz * sizeof(double), ctx->stream));
+  pencil_set_values(P, a, b, false);
+  P.d_sfirst.upload(ctx, S.sfirst);
+  P.d_rptr.upload(ctx, S.rptr);
+  P.d_rows.upload(ctx, S.rows);
+  P.d_lptr.upload(ctx, S.lptr);
+  P.d_uptr.upload(ctx, S.uptr);
+  P.d_eptr.upload(ctx, S.eptr);
+  P.d_emap.upload(ctx, S.emap);
+  P.d_cptr.upload(ctx, S.cptr);
+  P.d_clist.upload(ctx, S.clist);
+  P.d_acptr.upload(ctx, S.acptr);
+  P.d_asrc.upload(ctx, S.asrc);
+  P.d_adst.upload(ctx, S.adst);
+  P.d_perm.upload(ctx, S.perm);
+  build_schedule(P);
+  P.meta.sfirst = P.d_sfirst.get();
+  P.meta.rptr = P.d_rptr.get();
+  P.meta.rows = P.d_rows.get();
+  P.meta.lptr = P.d_lptr.get();
+  P.meta.uptr = P.d_uptr.get();
+  P.meta.wptr = P.d_wptr.get();
+  P.meta.eptr = P.d_eptr.get();
+  P.meta.emap = P.d_emap.get();
+  P.meta.cptr = P.d_cptr.get();
+  P.meta.clist = P.d_clist.get();
+  P.meta.acptr = P.d_acptr.get();
+  P.meta.asrc = P.d_asrc.get();
+  P.meta.adst = P.d_adst.get();
+  P.meta.tilew = P.d_tilew.get();
+  P.U.alloc(ctx, (size_t)S.pool_size);
+  P.W.alloc(ctx, (size_t)P.wsize);
+  P.sig.alloc(ctx, 8);
+  P.scratch.reset(new NumFactor());
+  factor_alloc(P, *P.scratch);
+  ctx->sync();
+}
+
+void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_ptrs) {
+  const size_t bytes = P.nnz * sizeof(double);
+  hipMemcpyKind kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  KTH_HIP(hipMemcpyAsync(P.aval.get(), a, bytes, kind, P.ctx->stream));
+  KTH_HIP(hipMemcpyAsync(P.bval.get(), b, bytes, kind, P.ctx->stream));
+  if (!device_ptrs) {
+    P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), a);
+    P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), b);
+  } else {
+    std::vector<double> ha(P.nnz), hb(P.nnz);
+    KTH_HIP(hipMemcpyAsync(ha.data(), a, bytes, hipMemcpyDeviceToHost, P.ctx->stream));
+    KTH_HIP(hipMemcpyAsync(hb.data(), b, bytes, hipMemcpyDeviceToHost, P.ctx->stream));
+    P.ctx->sync();
+    P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), ha.data());
+    P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), hb.data());
+  }
+}
+
+void factor_alloc(Pencil& P, NumFactor& F) {
+  Ctx* c = P.ctx;
+  F.p = &P;
+  F.L.alloc(c, (size_t)P.S.lptr[P.S.nsup]);
+  F.D.alloc(c, (size_t)P.n);
+  F.E.alloc(c, (size_t)P.n);
+  F.tperm.alloc(c, (size_t)P.n);
+  F.stats.alloc(c, 1);
+}
+
+void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b) {
+  Ctx* c = P.ctx;
+  hipStream_t st = c->stream;
+  F.sigma = sigma;
+  F.have_stats = false;
+  const double sv = mode_b ? -1.0 : sigma;   // B = fma(-(-1), b, 0)
+  const double* av = mode_b ? P.zeros.get() : P.aval.get();
+  const double* bv = P.bval.get();
+  launch_set_scalar(P.sig.get(), sv, st);
+  launch_fill_stats(F.stats.get(), st);
+  const int32_t* sched = P.d_sched.get();
+  for (const LevelPlan& lp : P.levels) {
+    launch_small_fronts(P.meta, sched + lp.small_off, lp.small_cnt, lp.small_maxnf, av, bv,
+                        P.sig.get(), F.L.get(), P.U.get(), F.D.get(), F.E.get(), F.tperm.get(),
+                        F.stats.get(), st);
+    if (lp.large_cnt == 0) continue;
+    launch_front_init(P.meta, reinterpret_cast<const Int2*>(sched + lp.init_off), lp.init_cnt, av,
+                      bv, P.sig.get(), F.L.get(), P.U.get(), st);
+    for (const StepPlan& sp : lp.steps) {
+      launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, F.L.get(), F.D.get(),
+                         F.E.get(), F.tperm.get(), F.stats.get(), st);
+      launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm_off), sp.trsm_cnt, sp.t,
+                        F.L.get(), P.W.get(), F.D.get(), F.E.get(), F.tperm.get(), F.stats.get(), st);
+      launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles, sp.t,
+                   F.L.get(), P.U.get(), P.W.get(), st);
+    }
+  }
+  KTH_HIP(hipGetLastError());
+}
+
+void factor_read_stats(Pencil& P, NumFactor& F) {
+  KTH_HIP(hipMemcpyAsync(&F.hs, F.stats.get(), sizeof(FactStats), hipMemcpyDeviceToHost, P.ctx->stream));
+  P.ctx->sync();
+  F.have_stats = true;
+  if ((int64_t)(F.hs.neg + F.hs.zero + F.hs.pos) != P.n)
+    throw Error(KTH_EDEVICE, "inertia counts do not add up to n (" + std::to_string(F.hs.neg) + "+" +
+                                 std::to_string(F.hs.zero) + "+" + std::to_string(F.hs.pos) + ")");
+}
+
+void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x) {
+  Ctx* c = P.ctx;
+  if (!F.xe.p) {
+    F.xe.alloc(c, (size_t)P.n);
+    F.ye.alloc(c, (size_t)P.n);
+    F.R.alloc(c, P.S.rows.size());
+  }
+  solve_enqueue<double>(P.splan, P.meta, F.L.get(), F.D.get(), F.E.get(), F.tperm.get(),
+                        P.d_perm.get(), P.n, b, x, F.xe.get(), F.ye.get(), F.R.get(), c->stream);
+}
+
+}  // namespace kth

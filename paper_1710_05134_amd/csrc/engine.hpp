@@ -1,0 +1,145 @@
+// Host orchestration of the device path: context (device, stream, allocator),
+// pencil (pattern analysis, schedule, device arrays) and numeric factors.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/kth.h"
+#include "analysis.hpp"
+#include "device.hpp"
+#include "solve.hpp"
+
+namespace kth {
+
+struct Error : std::runtime_error {
+  kth_status status;
+  Error(kth_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define KTH_HIP(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::kth::Error(KTH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  kth_alloc_fn afn = nullptr;
+  kth_free_fn ffn = nullptr;
+  void* user = nullptr;
+  std::string last_error;
+  double cur_bytes = 0, peak_bytes = 0;
+  void* alloc(size_t bytes);
+  void release(void* p, size_t bytes);
+  void sync();
+};
+
+// Device buffer owned through the context's allocator.
+template <typename T>
+struct DBuf {
+  Ctx* ctx = nullptr;
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p) ctx->release(p, n * sizeof(T));
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(Ctx* c, size_t count) {
+    reset();
+    ctx = c;
+    n = count ? count : 1;
+    p = static_cast<T*>(ctx->alloc(n * sizeof(T)));
+  }
+  void upload(Ctx* c, const T* host, size_t count) {
+    alloc(c, count);
+    if (count) KTH_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  }
+  void upload(Ctx* c, const std::vector<T>& v) { upload(c, v.data(), v.size()); }
+  T* get() const { return p; }
+  void swap(DBuf& o) {
+    std::swap(ctx, o.ctx);
+    std::swap(p, o.p);
+    std::swap(n, o.n);
+  }
+};
+
+struct StepPlan {
+  int32_t t;
+  int32_t nfronts;     // active large fronts (prefix of the level's sorted list)
+  int32_t trsm_off, trsm_cnt;   // Int2 tasks (offset in int32 units)
+  int32_t prefix_off, ntiles;   // tile prefix over active fronts
+};
+
+struct LevelPlan {
+  int32_t small_off = 0, small_cnt = 0, small_maxnf = 0;
+  int32_t init_off = 0, init_cnt = 0;
+  int32_t large_off = 0, large_cnt = 0;
+  std::vector<StepPlan> steps;
+};
+
+struct NumFactor;
+
+struct Pencil {
+  Ctx* ctx = nullptr;
+  int64_t n = 0, nnz = 0;
+  Symbolic S;
+  std::vector<int64_t> h_rowptr;
+  std::vector<int32_t> h_col;
+  double normA_inf = 0, normB_inf = 0;
+  // device CSR and values
+  DBuf<int64_t> rowptr;
+  DBuf<int32_t> col;
+  DBuf<double> aval, bval, zeros;
+  // device metadata
+  DBuf<int64_t> d_sfirst, d_rptr, d_lptr, d_uptr, d_wptr, d_eptr, d_cptr, d_acptr, d_asrc, d_adst,
+      d_perm;
+  DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched;
+  FrontMeta meta{};
+  std::vector<LevelPlan> levels;
+  SolvePlan splan;
+  int64_t wsize = 0;   // workspace doubles
+  DBuf<double> U, W;   // update-block pool, panel workspace
+  DBuf<double> sig;    // device scalars: [0] sigma of the running factorization
+  std::unique_ptr<NumFactor> scratch;   // factor reused by inertia-only calls
+  double flops() const { return S.flops; }
+};
+
+struct NumFactor {
+  Pencil* p = nullptr;
+  double sigma = 0;
+  kth_precision prec = KTH_FP64;
+  DBuf<double> L, D, E;
+  DBuf<int32_t> tperm;
+  DBuf<FactStats> stats;
+  FactStats hs{};
+  bool have_stats = false;
+  // solve scratch
+  DBuf<double> xe, ye, R;
+};
+
+void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
+                 const double* a, const double* b, uint32_t flags);
+void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_ptrs);
+void factor_alloc(Pencil& P, NumFactor& F);
+// Enqueue the numeric factorization of A - sigma B (mode_b: factor B itself).
+void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b);
+// Read back the inertia statistics (synchronises the stream).
+void factor_read_stats(Pencil& P, NumFactor& F);
+// x = (A - sigma B)^{-1} b, device vectors (enqueue only).
+void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x);
+
+}  // namespace kth

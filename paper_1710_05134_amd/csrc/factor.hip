@@ -1,0 +1,628 @@
+// Numeric multifrontal LDL^T of A - sigma B on gfx950 (FP64), and the sign
+// count of D (Sylvester's law of inertia, Section 2.1; Alg. 1').
+//
+// Per tree level, leaves first:
+//   * fronts with nf <= kSmallMaxNf: one workgroup each, the whole front in LDS:
+//     assemble originals fma(-sigma, b, a), add children's update blocks, then
+//     unblocked Bunch-Kaufman over the fully-summed columns, write the panel,
+//     D and the update block.
+//   * larger fronts: k_front_init assembles column chunks in HBM; then per
+//     pivot tile of kNB columns: k_tile_factor (Bunch-Kaufman inside the tile, in
+//     LDS), k_panel_trsm (rows below the tile: L21 = S21 P^T L11^{-T} D^{-1} and
+//     W = L21 D), k_schur (trailing lower triangle -= W L21^T on FP64 MFMA).
+// Row interchanges stay inside a tile; rows of earlier panels are not swapped --
+// the solve applies each tile's permutation when it reaches that tile.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace kth {
+
+namespace {
+
+constexpr double kAlphaBK = 0.6403882032022076;  // (1 + sqrt(17)) / 8
+
+__device__ inline unsigned long long dbits(double x) { return __double_as_longlong(x); }
+
+// Block-wide argmax of (v, idx): larger v wins, ties -> smaller idx (idx -1 = none).
+template <int NT>
+__device__ inline void block_argmax(double& v, int& idx, double* sv, int* si) {
+  for (int off = 32; off > 0; off >>= 1) {
+    double ov = __shfl_xor(v, off);
+    int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi >= 0 && (idx < 0 || oi < idx))) { v = ov; idx = oi; }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { sv[wave] = v; si[wave] = idx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NT / 64; w++) {
+      if (sv[w] > sv[0] || (sv[w] == sv[0] && si[w] >= 0 && (si[0] < 0 || si[w] < si[0]))) {
+        sv[0] = sv[w]; si[0] = si[w];
+      }
+    }
+  }
+  __syncthreads();
+  v = sv[0];
+  idx = si[0];
+  __syncthreads();
+}
+
+template <int NT>
+__device__ inline double block_max(double v, double* sv) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sv[wave] = v;
+  __syncthreads();
+  double r = sv[0];
+  for (int w = 1; w < NT / 64; w++) r = fmax(r, sv[w]);
+  __syncthreads();
+  return r;
+}
+
+// Symmetric interchange of rows/columns k < r of a lower-stored LDS matrix.
+template <int NT>
+__device__ inline void lds_sym_swap(double* F, int ld, int nrows, int k, int r) {
+  // tasks: [0,k): columns left of k;  k: diagonal;  (k,r): the band between;  (r,nrows): below r
+  for (int x = threadIdx.x; x < nrows - 1; x += NT) {
+    if (x < k) {
+      double t = F[k + x * ld]; F[k + x * ld] = F[r + x * ld]; F[r + x * ld] = t;
+    } else if (x == k) {
+      double t = F[k + k * ld]; F[k + k * ld] = F[r + r * ld]; F[r + r * ld] = t;
+    } else if (x < r) {
+      double t = F[x + k * ld]; F[x + k * ld] = F[r + x * ld]; F[r + x * ld] = t;
+    } else {
+      int i = x + 1;
+      double t = F[i + k * ld]; F[i + k * ld] = F[i + r * ld]; F[i + r * ld] = t;
+    }
+  }
+}
+
+struct BKCounts {
+  unsigned long long neg, zero, pos, n2x2;
+  double mind, maxl;
+};
+
+// Unblocked Bunch-Kaufman LDL^T of the leading `ncand` columns of the nrows x nrows
+// lower-stored LDS matrix F; candidate pivot rows are the first ncand rows; all
+// nrows rows are eliminated against them (rows >= ncand form L21 and the Schur
+// complement).  lp[] receives the pivot order, d[]/e[] the blocks of D.
+// On return F holds unit-lower L in the eliminated columns and the Schur
+// complement in the trailing block.  Counts accumulate in thread 0's cnt.
+template <int NT>
+__device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, double* d,
+                              double* e, double* lcol, BKCounts& cnt, double* sv, int* si) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = NT / 64;
+  double maxl = 0.0;
+  for (int q = tid; q < ncand; q += NT) lp[q] = q;
+  __syncthreads();
+  int k = 0;
+  while (k < ncand) {
+    // gamma_1 = max_{k < i < ncand} |F(i,k)|
+    double v = -1.0;
+    int idx = -1;
+    for (int i = k + 1 + tid; i < ncand; i += NT) {
+      double x = fabs(F[i + k * ld]);
+      if (x > v) { v = x; idx = i; }
+    }
+    block_argmax<NT>(v, idx, sv, si);
+    const double g1 = idx < 0 ? 0.0 : v;
+    const int r = idx < 0 ? k : idx;
+    const double akk = fabs(F[k + k * ld]);
+    int kind = 0;  // 0: 1x1 at k; 1: 1x1 at r (swap k,r); 2: 2x2 (k, r -> k+1)
+    if (!(g1 == 0.0 || akk >= kAlphaBK * g1)) {
+      double gv = 0.0;
+      for (int i = k + tid; i < ncand; i += NT) {
+        if (i == r) continue;
+        double x = i < r ? fabs(F[r + i * ld]) : fabs(F[i + r * ld]);
+        gv = fmax(gv, x);
+      }
+      const double gr = block_max<NT>(gv, sv);
+      if (akk * gr >= kAlphaBK * g1 * g1) kind = 0;
+      else if (fabs(F[r + r * ld]) >= kAlphaBK * gr) kind = 1;
+      else kind = 2;
+    }
+    __syncthreads();  // every thread has read the pivot candidates before any swap
+    if (kind == 1) {
+      lds_sym_swap<NT>(F, ld, nrows, k, r);
+      if (tid == 0) { int t = lp[k]; lp[k] = lp[r]; lp[r] = t; }
+      __syncthreads();
+    } else if (kind == 2 && r != k + 1) {
+      lds_sym_swap<NT>(F, ld, nrows, k + 1, r);
+      if (tid == 0) { int t = lp[k + 1]; lp[k + 1] = lp[r]; lp[r] = t; }
+      __syncthreads();
+    }
+    if (kind < 2) {
+      const double dk = F[k + k * ld];
+      if (tid == 0) {
+        d[k] = dk; e[k] = 0.0;
+        if (dk < 0) cnt.neg++; else if (dk > 0) cnt.pos++; else cnt.zero++;
+        cnt.mind = fmin(cnt.mind, fabs(dk));
+      }
+      if (dk != 0.0) {
+        for (int i = k + 1 + tid; i < nrows; i += NT) lcol[i] = F[i + k * ld] / dk;
+        __syncthreads();
+        for (int j = k + 1 + wave; j < nrows; j += NW) {
+          const double fj = F[j + k * ld];
+          for (int i = j + lane; i < nrows; i += 64) F[i + j * ld] -= lcol[i] * fj;
+        }
+        __syncthreads();
+        for (int i = k + 1 + tid; i < nrows; i += NT) {
+          F[i + k * ld] = lcol[i];
+          maxl = fmax(maxl, fabs(lcol[i]));
+        }
+      } else {
+        for (int i = k + 1 + tid; i < nrows; i += NT) F[i + k * ld] = 0.0;
+      }
+      if (tid == 0) F[k + k * ld] = 1.0;
+      __syncthreads();
+      k += 1;
+    } else {
+      const double a = F[k + k * ld], b = F[(k + 1) + k * ld], c = F[(k + 1) + (k + 1) * ld];
+      const double det = a * c - b * b;
+      if (tid == 0) {
+        d[k] = a; e[k] = b; d[k + 1] = c; e[k + 1] = 0.0;
+        const double tr = a + c;
+        if (det < 0) { cnt.neg++; cnt.pos++; }
+        else if (det > 0) { if (tr < 0) cnt.neg += 2; else cnt.pos += 2; }
+        else { cnt.zero++; if (tr < 0) cnt.neg++; else if (tr > 0) cnt.pos++; else cnt.zero++; }
+        cnt.n2x2++;
+        const double m = 0.5 * tr, q = sqrt(0.25 * (a - c) * (a - c) + b * b);
+        cnt.mind = fmin(cnt.mind, fmin(fabs(m - q), fabs(m + q)));
+      }
+      double* lcol2 = lcol + ld;
+      for (int i = k + 2 + tid; i < nrows; i += NT) {
+        const double w1 = F[i + k * ld], w2 = F[i + (k + 1) * ld];
+        lcol[i] = (c * w1 - b * w2) / det;
+        lcol2[i] = (a * w2 - b * w1) / det;
+      }
+      __syncthreads();
+      for (int j = k + 2 + wave; j < nrows; j += NW) {
+        const double w1 = F[j + k * ld], w2 = F[j + (k + 1) * ld];
+        for (int i = j + lane; i < nrows; i += 64) F[i + j * ld] -= lcol[i] * w1 + lcol2[i] * w2;
+      }
+      __syncthreads();
+      for (int i = k + 2 + tid; i < nrows; i += NT) {
+        F[i + k * ld] = lcol[i];
+        F[i + (k + 1) * ld] = lcol2[i];
+        maxl = fmax(maxl, fmax(fabs(lcol[i]), fabs(lcol2[i])));
+      }
+      if (tid == 0) { F[k + k * ld] = 1.0; F[(k + 1) + k * ld] = 0.0; F[(k + 1) + (k + 1) * ld] = 1.0; }
+      __syncthreads();
+      k += 2;
+    }
+  }
+  maxl = block_max<NT>(maxl, sv);
+  if (tid == 0) cnt.maxl = fmax(cnt.maxl, maxl);
+}
+
+__device__ inline void flush_counts(const BKCounts& c, FactStats* st) {
+  if (c.neg) atomicAdd(&st->neg, c.neg);
+  if (c.zero) atomicAdd(&st->zero, c.zero);
+  if (c.pos) atomicAdd(&st->pos, c.pos);
+  if (c.n2x2) atomicAdd(&st->n2x2, c.n2x2);
+  atomicMin(&st->min_d_bits, dbits(c.mind));
+  atomicMax(&st->max_l_bits, dbits(c.maxl));
+}
+
+__global__ void k_fill_stats(FactStats* st) {
+  if (threadIdx.x == 0) {
+    st->neg = st->zero = st->pos = st->n2x2 = 0;
+    st->min_d_bits = dbits(INFINITY);
+    st->max_l_bits = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small fronts: everything in LDS.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void k_small_fronts(FrontMeta M, const int32_t* fronts,
+                                                     const double* __restrict__ aval,
+                                                     const double* __restrict__ bval,
+                                                     const double* sigma_dev, double* L, double* U,
+                                                     double* D, double* E, int32_t* tperm,
+                                                     FactStats* st) {
+  extern __shared__ double smem[];
+  __shared__ double sv[NT / 64];
+  __shared__ int si[NT / 64];
+  __shared__ int lp[kSmallMaxNf];
+  __shared__ double dd[kSmallMaxNf], ee[kSmallMaxNf];
+  __shared__ double lcol[2 * kSmallMaxNf];
+  const int s = fronts[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int nu = nf - ns;
+  const double sigma = *sigma_dev;
+  double* F = smem;
+  for (int q = tid; q < nf * nf; q += NT) F[q] = 0.0;
+  __syncthreads();
+  for (int64_t e = M.acptr[f0] + tid; e < M.acptr[f0 + ns]; e += NT) {
+    const int64_t p = M.asrc[e];
+    F[M.adst[e]] = fma(-sigma, bval[p], aval[p]);
+  }
+  __syncthreads();
+  for (int64_t q = M.cptr[s]; q < M.cptr[s + 1]; q++) {
+    const int c = M.clist[q];
+    const int nuc = (int)(M.rptr[c + 1] - M.rptr[c] - (M.sfirst[c + 1] - M.sfirst[c]));
+    const double* Uc = U + M.uptr[c];
+    const int32_t* map = M.emap + M.eptr[c];
+    for (int x = tid; x < nuc * nuc; x += NT) {
+      const int a = x % nuc, b = x / nuc;
+      if (a >= b) F[map[a] + map[b] * nf] += Uc[a + (int64_t)b * nuc];
+    }
+    __syncthreads();
+  }
+  BKCounts cnt{0, 0, 0, 0, INFINITY, 0.0};
+  bk_factor_lds<NT>(F, nf, nf, ns, lp, dd, ee, lcol, cnt, sv, si);
+  double* Lp = L + M.lptr[s];
+  for (int q = tid; q < nf * ns; q += NT) Lp[q] = F[q];
+  for (int q = tid; q < ns; q += NT) {
+    D[f0 + q] = dd[q];
+    E[f0 + q] = ee[q];
+    tperm[f0 + q] = lp[q];
+  }
+  if (M.uptr[s] >= 0 && nu > 0) {
+    double* Ub = U + M.uptr[s];
+    for (int x = tid; x < nu * nu; x += NT) {
+      const int a = x % nu, b = x / nu;
+      if (a >= b) Ub[x] = F[(ns + a) + (ns + b) * nf];
+    }
+  }
+  if (tid == 0) flush_counts(cnt, st);
+}
+
+// ---------------------------------------------------------------------------
+// Large fronts: assembly of a column chunk.
+// ---------------------------------------------------------------------------
+struct FrontRef {
+  double* Lp;  // panel, ld nf
+  double* Ub;  // update block, ld nu (may be null)
+  int nf, ns, nu;
+  __device__ inline double* at(int i, int j) const {
+    return j < ns ? Lp + i + (int64_t)j * nf : Ub + (i - ns) + (int64_t)(j - ns) * nu;
+  }
+};
+
+__device__ inline FrontRef front_ref(const FrontMeta& M, int s, double* L, double* U) {
+  FrontRef f;
+  const int64_t f0 = M.sfirst[s];
+  f.ns = (int)(M.sfirst[s + 1] - f0);
+  f.nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  f.nu = f.nf - f.ns;
+  f.Lp = L + M.lptr[s];
+  f.Ub = M.uptr[s] >= 0 ? U + M.uptr[s] : nullptr;
+  return f;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* tasks,
+                                                   const double* __restrict__ aval,
+                                                   const double* __restrict__ bval,
+                                                   const double* sigma_dev, double* L, double* U) {
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a, c0 = tk.b;
+  const FrontRef f = front_ref(M, s, L, U);
+  const int c1 = min(c0 + kAsmCols, f.nf);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = NT / 64;
+  const double sigma = *sigma_dev;
+  // a root's update block does not exist: its columns beyond ns never occur (nu == 0)
+  for (int j = c0 + wave; j < c1; j += NW)
+    for (int i = j + lane; i < f.nf; i += 64) *f.at(i, j) = 0.0;
+  __syncthreads();
+  if (c0 < f.ns) {
+    const int64_t f0 = M.sfirst[s];
+    const int64_t e1 = M.acptr[f0 + min(c1, f.ns)];
+    for (int64_t e = M.acptr[f0 + c0] + tid; e < e1; e += NT) {
+      const int64_t p = M.asrc[e];
+      f.Lp[M.adst[e]] = fma(-sigma, bval[p], aval[p]);
+    }
+  }
+  __syncthreads();
+  for (int64_t q = M.cptr[s]; q < M.cptr[s + 1]; q++) {
+    const int c = M.clist[q];
+    const int nuc = (int)(M.rptr[c + 1] - M.rptr[c] - (M.sfirst[c + 1] - M.sfirst[c]));
+    const double* Uc = U + M.uptr[c];
+    const int32_t* map = M.emap + M.eptr[c];
+    // child columns b whose parent column map[b] lies in [c0, c1)
+    int lo = 0, hi = nuc;
+    while (lo < hi) { int mid = (lo + hi) >> 1; if (map[mid] < c0) lo = mid + 1; else hi = mid; }
+    const int b0 = lo;
+    hi = nuc;
+    while (lo < hi) { int mid = (lo + hi) >> 1; if (map[mid] < c1) lo = mid + 1; else hi = mid; }
+    const int b1 = lo;
+    for (int b = b0 + wave; b < b1; b += NW) {
+      const int jc = map[b];
+      for (int a = b + lane; a < nuc; a += 64) *f.at(map[a], jc) += Uc[a + (int64_t)b * nuc];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Large fronts: Bunch-Kaufman inside pivot tile t (kNB columns), in LDS.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* fronts, int t,
+                                                    double* L, double* D, double* E,
+                                                    int32_t* tperm, FactStats* st) {
+  __shared__ double T[kNB * kNB];
+  __shared__ double sv[NT / 64];
+  __shared__ int si[NT / 64];
+  __shared__ int lp[kNB];
+  __shared__ double dd[kNB], ee[kNB];
+  __shared__ double lcol[2 * kNB];
+  const int s = fronts[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB;
+  const int kb = min(kNB, ns - k0);
+  double* Lp = L + M.lptr[s];
+  for (int x = tid; x < kb * kb; x += NT) {
+    const int i = x % kb, j = x / kb;
+    T[i + j * kb] = i >= j ? Lp[(k0 + i) + (int64_t)(k0 + j) * nf] : 0.0;
+  }
+  __syncthreads();
+  BKCounts cnt{0, 0, 0, 0, INFINITY, 0.0};
+  bk_factor_lds<NT>(T, kb, kb, kb, lp, dd, ee, lcol, cnt, sv, si);
+  for (int x = tid; x < kb * kb; x += NT) {
+    const int i = x % kb, j = x / kb;
+    if (i >= j) Lp[(k0 + i) + (int64_t)(k0 + j) * nf] = T[i + j * kb];
+  }
+  for (int q = tid; q < kb; q += NT) {
+    D[f0 + k0 + q] = dd[q];
+    E[f0 + k0 + q] = ee[q];
+    tperm[f0 + k0 + q] = lp[q];
+  }
+  if (tid == 0) flush_counts(cnt, st);
+}
+
+// ---------------------------------------------------------------------------
+// Large fronts: rows below pivot tile t.  For row i: s = S(i, k0 + perm[.]),
+// w = s L_tt^{-T}, l = w D^{-1}; panel row <- l, workspace W row <- w.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* tasks, int t,
+                                                   double* L, double* W,
+                                                   const double* __restrict__ D,
+                                                   const double* __restrict__ E,
+                                                   const int32_t* __restrict__ tperm,
+                                                   FactStats* st) {
+  __shared__ double Lt[kNB * kNB];
+  __shared__ double dd[kNB], ee[kNB];
+  __shared__ int pp[kNB];
+  __shared__ double sv[NT / 64];
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a;
+  const int tid = threadIdx.x;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB;
+  const int kb = min(kNB, ns - k0);
+  double* Lp = L + M.lptr[s];
+  double* Wp = W + M.wptr[s];
+  for (int x = tid; x < kNB * kNB; x += NT) {
+    const int i = x % kNB, j = x / kNB;
+    Lt[x] = (i < kb && j < kb && i > j) ? Lp[(k0 + i) + (int64_t)(k0 + j) * nf] : 0.0;
+  }
+  for (int q = tid; q < kNB; q += NT) {
+    dd[q] = q < kb ? D[f0 + k0 + q] : 1.0;
+    ee[q] = q < kb ? E[f0 + k0 + q] : 0.0;
+    pp[q] = q < kb ? tperm[f0 + k0 + q] : 0;
+  }
+  __syncthreads();
+  const int i = tk.b + tid;
+  double maxl = 0.0;
+  if (i < nf) {
+    double w[kNB];
+#pragma unroll
+    for (int q = 0; q < kNB; q++) w[q] = q < kb ? Lp[i + (int64_t)(k0 + pp[q]) * nf] : 0.0;
+    // w L_tt^T = s  (L_tt unit lower)
+#pragma unroll
+    for (int p = 0; p < kNB; p++) {
+      const double wp = w[p];
+#pragma unroll
+      for (int q = p + 1; q < kNB; q++) w[q] -= Lt[q + p * kNB] * wp;
+    }
+#pragma unroll
+    for (int q = 0; q < kNB; q++) {
+      if (q < kb) {
+        Wp[i + (int64_t)q * nf] = w[q];
+      }
+    }
+    // l = w D^{-1}
+#pragma unroll
+    for (int q = 0; q < kNB; q++) {
+      if (q < kb) {
+        double l;
+        if (q + 1 < kNB && ee[q] != 0.0) {   // 2x2 block (q, q+1)
+          const double a = dd[q], b = ee[q], c = dd[q + 1], det = a * c - b * b;
+          l = (c * w[q] - b * w[q + 1]) / det;
+        } else if (q > 0 && ee[q - 1] != 0.0) {  // second row of a 2x2 block
+          const double a = dd[q - 1], b = ee[q - 1], c = dd[q], det = a * c - b * b;
+          l = (a * w[q] - b * w[q - 1]) / det;
+        } else {
+          l = dd[q] != 0.0 ? w[q] / dd[q] : 0.0;
+        }
+        Lp[i + (int64_t)(k0 + q) * nf] = l;
+        maxl = fmax(maxl, fabs(l));
+      }
+    }
+  }
+  maxl = block_max<NT>(maxl, sv);
+  if (tid == 0) atomicMax(&st->max_l_bits, dbits(maxl));
+}
+
+// ---------------------------------------------------------------------------
+// Large fronts: trailing update after tile t on FP64 MFMA (v_mfma_f64_16x16x4).
+// The trailing range [r0, nf) is cut into 64-chunks aligned at ns (so no chunk
+// mixes panel and update-block columns); one workgroup per lower tile (bi >= bj).
+// ---------------------------------------------------------------------------
+typedef double double4v __attribute__((ext_vector_type(4)));
+
+__device__ inline void chunk_range(int c, int r0, int ns, int nf, int nc1, int& b, int& e) {
+  if (c < nc1) { b = r0 + c * kTile; e = min(b + kTile, ns); }
+  else { b = ns + (c - nc1) * kTile; e = min(b + kTile, nf); }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts,
+                                              const int32_t* tile_prefix, int nfronts, int t,
+                                              double* L, double* U, const double* W) {
+  __shared__ double As[kTile * kNB];  // W rows (i) x k, ld kTile
+  __shared__ double Bs[kTile * kNB];  // L rows (j) x k, ld kTile
+  // locate the front of this tile
+  const int g = blockIdx.x;
+  int lo = 0, hi = nfronts - 1;
+  while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (tile_prefix[mid] <= g) lo = mid; else hi = mid - 1; }
+  const int s = fronts[lo];
+  const int tl = g - tile_prefix[lo];
+  const FrontRef f = front_ref(M, s, L, U);
+  const int k0 = t * kNB;
+  const int kb = min(kNB, f.ns - k0);
+  const int r0 = k0 + kb;
+  const int nc1 = r0 < f.ns ? (f.ns - r0 + kTile - 1) / kTile : 0;
+  // tile index -> (bi, bj), bi >= bj
+  int bi = (int)((sqrt(8.0 * tl + 1.0) - 1.0) * 0.5);
+  while ((bi + 1) * (bi + 2) / 2 <= tl) bi++;
+  while (bi * (bi + 1) / 2 > tl) bi--;
+  const int bj = tl - bi * (bi + 1) / 2;
+  int ib, ie, jb, je;
+  chunk_range(bi, r0, f.ns, f.nf, nc1, ib, ie);
+  chunk_range(bj, r0, f.ns, f.nf, nc1, jb, je);
+  const double* Lp = f.Lp;
+  const double* Wp = W + M.wptr[s];
+  const int tid = threadIdx.x;
+  for (int x = tid; x < kTile * kNB; x += NT) {
+    const int r = x % kTile, q = x / kTile;
+    const bool qok = q < kb;
+    As[x] = (qok && ib + r < ie) ? Wp[(ib + r) + (int64_t)q * f.nf] : 0.0;
+    Bs[x] = (qok && jb + r < je) ? Lp[(jb + r) + (int64_t)(k0 + q) * f.nf] : 0.0;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;  // wave's 32x32 sub-tile
+  double4v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) acc[a][b] = (double4v){0.0, 0.0, 0.0, 0.0};
+  const int m = lane & 15, kk = lane >> 4;
+  for (int q0 = 0; q0 < kNB; q0 += 4) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; a++) av[a] = As[(wr + a * 16 + m) + (q0 + kk) * kTile];
+#pragma unroll
+    for (int b = 0; b < 2; b++) bv[b] = Bs[(wc + b * 16 + m) + (q0 + kk) * kTile];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+  // write back: C(i, j) -= acc for i >= j inside the chunk bounds
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      const int j = jb + wc + b * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int i = ib + wr + a * 16 + 4 * r + (lane >> 4);   // register r: row 4r + lane/16
+        if (i < ie && j < je && i >= j) {
+          double* p = f.at(i, j);
+          *p -= acc[a][b][r];
+        }
+      }
+    }
+}
+
+__global__ void k_set_scalar(double* p, double v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+// Raw probe: lane l feeds a[l] and b[l]; c[4 l + r] receives result register r.
+__global__ void k_mfma_probe(const double* A, const double* B, double* Dout) {
+  const int lane = threadIdx.x;
+  double4v c = {0.0, 0.0, 0.0, 0.0};
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(A[lane], B[lane], c, 0, 0, 0);
+  for (int r = 0; r < 4; r++) Dout[4 * lane + r] = c[r];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_fill_stats(FactStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_stats, dim3(1), dim3(64), 0, s, st);
+}
+
+void launch_small_fronts(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t max_nf,
+                         const double* aval, const double* bval, const double* sigma_dev,
+                         double* L, double* U, double* D, double* E, int32_t* tperm,
+                         FactStats* st, hipStream_t s) {
+  if (count <= 0) return;
+  const size_t lds = (size_t)max_nf * max_nf * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_small_fronts<256>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kSmallMaxNf * kSmallMaxNf * (int)sizeof(double));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_small_fronts<256>, dim3(count), dim3(256), lds, s, M, fronts, aval, bval,
+                     sigma_dev, L, U, D, E, tperm, st);
+}
+
+void launch_front_init(const FrontMeta& M, const Int2* tasks, int32_t count, const double* aval,
+                       const double* bval, const double* sigma_dev, double* L, double* U,
+                       hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_front_init<256>, dim3(count), dim3(256), 0, s, M, tasks, aval, bval,
+                     sigma_dev, L, U);
+}
+
+void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t t,
+                        double* L, double* D, double* E, int32_t* tperm, FactStats* st,
+                        hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_tile_factor<256>, dim3(count), dim3(256), 0, s, M, fronts, t, L, D, E,
+                     tperm, st);
+}
+
+void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, double* L,
+                       double* W, const double* D, const double* E, const int32_t* tperm,
+                       FactStats* st, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_panel_trsm<kTrsmRows>, dim3(count), dim3(kTrsmRows), 0, s, M, tasks, t, L,
+                     W, D, E, tperm, st);
+}
+
+void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
+                  int32_t nfronts, int32_t ntiles, int32_t t, double* L, double* U, const double* W,
+                  hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_schur<256>, dim3(ntiles), dim3(256), 0, s, M, fronts, tile_prefix, nfronts,
+                     t, L, U, W);
+}
+
+void launch_set_scalar(double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, p, v);
+}
+
+void launch_mfma_probe(const double* A, const double* B, double* D, hipStream_t s) {
+  hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, A, B, D);
+}
+
+}  // namespace kth

@@ -1,0 +1,194 @@
+// Triangular solves with a kept multifrontal factor: (A - sigma B) x = b as
+// L z = P b (forward, leaves to root), y = D^{-1} z, L^T w = y with x = P^T w
+// (backward, root to leaves).  The forward pass is itself multifrontal: each
+// front gathers its right-hand side, adds its children's update vectors (the
+// tails of their work vectors) and hands its own tail to its parent, so no two
+// fronts ever write the same entry.  Tile permutations are applied when the
+// solve reaches each tile (the factor keeps earlier panels' rows unswapped).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+#include "solve.hpp"
+
+namespace kth {
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline void tile_bounds(int t, int tw, int ns, int& k0, int& kb) {
+  k0 = t * tw;
+  kb = min(tw, ns - k0);
+}
+
+// Forward pass + diagonal for the fronts of one level.  xe: right-hand side in
+// elimination order; R: work vectors (front s at rptr[s], nf entries);
+// ye: output D^{-1} z in pivot order.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_solve_fwd(FrontMeta M, const int32_t* fronts, const T* L,
+                                                  const double* __restrict__ D,
+                                                  const double* __restrict__ E,
+                                                  const int32_t* __restrict__ tperm,
+                                                  const double* __restrict__ xe, double* R,
+                                                  double* ye) {
+  __shared__ double z[kSmallMaxNf];
+  const int s = fronts[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int tw = M.tilew[s];
+  double* Rs = R + M.rptr[s];
+  const T* Lp = L + M.lptr[s];
+  for (int i = tid; i < nf; i += NT) Rs[i] = i < ns ? xe[f0 + i] : 0.0;
+  __syncthreads();
+  for (int64_t q = M.cptr[s]; q < M.cptr[s + 1]; q++) {
+    const int c = M.clist[q];
+    const int nsc = (int)(M.sfirst[c + 1] - M.sfirst[c]);
+    const int nuc = (int)(M.rptr[c + 1] - M.rptr[c]) - nsc;
+    const double* Rc = R + M.rptr[c] + nsc;
+    const int32_t* map = M.emap + M.eptr[c];
+    for (int a = tid; a < nuc; a += NT) Rs[map[a]] += Rc[a];
+    __syncthreads();
+  }
+  const int ntiles = (ns + tw - 1) / tw;
+  for (int t = 0; t < ntiles; t++) {
+    int k0, kb;
+    tile_bounds(t, tw, ns, k0, kb);
+    // z = P_t r_t, then L_tt z = P_t r_t by one wave; lane holds z_lane, z_{lane+64}
+    if (wave == 0) {
+      double z0 = lane < kb ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
+      double z1 = lane + 64 < kb ? Rs[k0 + tperm[f0 + k0 + lane + 64]] : 0.0;
+      for (int p = 0; p < kb; p++) {
+        const double zp = p < 64 ? __shfl(z0, p) : __shfl(z1, p - 64);
+        if (lane > p && lane < kb) z0 -= (double)Lp[(k0 + lane) + (int64_t)(k0 + p) * nf] * zp;
+        if (lane + 64 > p && lane + 64 < kb)
+          z1 -= (double)Lp[(k0 + lane + 64) + (int64_t)(k0 + p) * nf] * zp;
+      }
+      if (lane < kb) z[lane] = z0;
+      if (lane + 64 < kb) z[lane + 64] = z1;
+    }
+    __syncthreads();
+    // rows below the tile
+    for (int i = k0 + kb + tid; i < nf; i += NT) {
+      double acc = 0.0;
+      for (int q = 0; q < kb; q++) acc += (double)Lp[i + (int64_t)(k0 + q) * nf] * z[q];
+      Rs[i] -= acc;
+    }
+    for (int q = tid; q < kb; q += NT) Rs[k0 + q] = z[q];
+    __syncthreads();
+  }
+  // y = D^{-1} z (pivot order)
+  for (int q = tid; q < ns; q += NT) {
+    const int64_t k = f0 + q;
+    double y;
+    if (E[k] != 0.0) {
+      const double a = D[k], b = E[k], c = D[k + 1], det = a * c - b * b;
+      y = (c * Rs[q] - b * Rs[q + 1]) / det;
+    } else if (q > 0 && E[k - 1] != 0.0 && ((q % tw) != 0)) {
+      const double a = D[k - 1], b = E[k - 1], c = D[k], det = a * c - b * b;
+      y = (a * Rs[q] - b * Rs[q - 1]) / det;
+    } else {
+      y = D[k] != 0.0 ? Rs[q] / D[k] : 0.0;
+    }
+    ye[k] = y;
+  }
+}
+
+// Backward pass for the fronts of one level (root side first).  ye: D^{-1} z in
+// pivot order; xe: solution in elimination order (ancestors already final).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_solve_bwd(FrontMeta M, const int32_t* fronts, const T* L,
+                                                  const int32_t* __restrict__ tperm,
+                                                  const double* __restrict__ ye, double* xe) {
+  __shared__ double g[kSmallMaxNf];
+  const int s = fronts[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int tw = M.tilew[s];
+  const int32_t* rows = M.rows + M.rptr[s];
+  const T* Lp = L + M.lptr[s];
+  const int ntiles = (ns + tw - 1) / tw;
+  for (int t = ntiles - 1; t >= 0; t--) {
+    int k0, kb;
+    tile_bounds(t, tw, ns, k0, kb);
+    // g_q = y_q - sum_{i >= k0+kb} L(i, k0+q) x(rows[i])  -- one column per lane group
+    for (int q = wave; q < kb; q += NT / 64) {
+      double acc = 0.0;
+      for (int i = k0 + kb + lane; i < nf; i += 64)
+        acc += (double)Lp[i + (int64_t)(k0 + q) * nf] * xe[rows[i]];
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (lane == 0) g[q] = ye[f0 + k0 + q] - acc;
+    }
+    __syncthreads();
+    // L_tt^T w = g, backward, by one wave; lane holds g_lane, g_{lane+64}
+    if (wave == 0) {
+      double g0 = lane < kb ? g[lane] : 0.0;
+      double g1 = lane + 64 < kb ? g[lane + 64] : 0.0;
+      for (int p = kb - 1; p >= 0; p--) {
+        const double wp = p < 64 ? __shfl(g0, p) : __shfl(g1, p - 64);
+        if (lane < p) g0 -= (double)Lp[(k0 + p) + (int64_t)(k0 + lane) * nf] * wp;
+        if (lane + 64 < p) g1 -= (double)Lp[(k0 + p) + (int64_t)(k0 + lane + 64) * nf] * wp;
+      }
+      if (lane < kb) g[lane] = g0;
+      if (lane + 64 < kb) g[lane + 64] = g1;
+    }
+    __syncthreads();
+    for (int q = tid; q < kb; q += NT) xe[f0 + k0 + tperm[f0 + k0 + q]] = g[q];
+    __syncthreads();
+  }
+}
+
+__global__ void k_gather(int64_t n, const int64_t* __restrict__ perm, const double* __restrict__ x,
+                         double* __restrict__ xe) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    xe[k] = x[perm[k]];
+}
+
+__global__ void k_scatter(int64_t n, const int64_t* __restrict__ perm, const double* __restrict__ xe,
+                          double* __restrict__ x) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    x[perm[k]] = xe[k];
+}
+
+inline int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+}
+
+}  // namespace
+
+template <typename T>
+void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const double* D,
+                   const double* E, const int32_t* tperm, const int64_t* perm, int64_t n,
+                   const double* b, double* x, double* xe, double* ye, double* R, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(256), 0, s, n, perm, b, xe);
+  for (size_t l = 0; l < P.level_off.size(); l++) {
+    const int cnt = P.level_cnt[l];
+    if (cnt > 0)
+      hipLaunchKernelGGL((k_solve_fwd<T>), dim3(cnt), dim3(NT), 0, s, M, P.fronts + P.level_off[l],
+                         L, D, E, tperm, xe, R, ye);
+  }
+  for (size_t l = P.level_off.size(); l-- > 0;) {
+    const int cnt = P.level_cnt[l];
+    if (cnt > 0)
+      hipLaunchKernelGGL((k_solve_bwd<T>), dim3(cnt), dim3(NT), 0, s, M, P.fronts + P.level_off[l],
+                         L, tperm, ye, xe);
+  }
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, s, n, perm, xe, x);
+}
+
+template void solve_enqueue<double>(const SolvePlan&, const FrontMeta&, const double*, const double*,
+                                    const double*, const int32_t*, const int64_t*, int64_t,
+                                    const double*, double*, double*, double*, double*, hipStream_t);
+template void solve_enqueue<float>(const SolvePlan&, const FrontMeta&, const float*, const double*,
+                                   const double*, const int32_t*, const int64_t*, int64_t,
+                                   const double*, double*, double*, double*, double*, hipStream_t);
+
+}  // namespace kth
