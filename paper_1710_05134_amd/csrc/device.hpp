@@ -22,6 +22,7 @@ struct FrontMeta {
   const int64_t* asrc;
   const int64_t* adst;
   const int32_t* tilew;   // [nsup] pivot-tile width (ns for fronts factored in one piece)
+  const int64_t* tptr;    // [nsup]   tile-inverse offsets (kNB*kNB per large front; -1 otherwise)
 };
 
 // Results of one numeric factorization that the host reads back.
@@ -39,7 +40,9 @@ constexpr int kNB = 64;
 // Column chunk of the large-front assembly kernel.
 constexpr int kAsmCols = 16;
 // Rows per workgroup of the panel triangular solve.
-constexpr int kTrsmRows = 256;
+constexpr int kTrsmRows = 64;
+// Rows per gather task of the large-front solve.
+constexpr int kSolveChunk = 256;
 // Schur-update output tile.
 constexpr int kTile = 64;
 
@@ -55,11 +58,11 @@ void launch_front_init(const FrontMeta& M, const Int2* tasks, int32_t count, con
                        const double* bval, const double* sigma_dev, double* L, double* U,
                        hipStream_t s);
 void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t t,
-                        double* L, double* D, double* E, int32_t* tperm, FactStats* st,
-                        hipStream_t s);
+                        double* L, double* D, double* E, int32_t* tperm, double* tinv,
+                        FactStats* st, hipStream_t s);
 void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, double* L,
                        double* W, const double* D, const double* E, const int32_t* tperm,
-                       FactStats* st, hipStream_t s);
+                       const double* tinv, FactStats* st, hipStream_t s);
 void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
                   int32_t nfronts, int32_t ntiles, int32_t t, double* L, double* U, const double* W,
                   hipStream_t s);

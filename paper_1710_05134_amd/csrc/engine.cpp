@@ -48,9 +48,11 @@ static void build_schedule(Pencil& P) {
   auto align2 = [&]() { if (sched.size() & 1) sched.push_back(0); };
   std::vector<std::vector<int32_t>> bylevel(S.nlevels);
   for (int64_t s = 0; s < S.nsup; s++) bylevel[S.level[s]].push_back((int32_t)s);
-  std::vector<int64_t> wptr(S.nsup, -1);
+  std::vector<int64_t> wptr(S.nsup, -1), tptr(S.nsup, -1);
   std::vector<int32_t> tilew(S.nsup, 0);
   P.wsize = 1;
+  P.tsize = 1;
+  P.splan.partial_size = 1;
   P.levels.assign(S.nlevels, LevelPlan());
   for (int64_t L = 0; L < S.nlevels; L++) {
     LevelPlan& lp = P.levels[L];
@@ -66,14 +68,17 @@ static void build_schedule(Pencil& P) {
     std::stable_sort(large.begin(), large.end(), [&](int32_t a, int32_t b) { return S.ns(a) > S.ns(b); });
     lp.large_off = (int32_t)sched.size();
     lp.large_cnt = (int32_t)large.size();
-    int64_t woff = 0;
+    int64_t woff = 0, toff = 0;
     for (int32_t s : large) {
       sched.push_back(s);
       tilew[s] = kNB;
       wptr[s] = woff;
       woff += S.nf(s) * kNB;
+      tptr[s] = toff;
+      toff += kNB * kNB;
     }
     P.wsize = std::max(P.wsize, woff);
+    P.tsize = std::max(P.tsize, toff);
     align2();
     lp.init_off = (int32_t)sched.size();
     for (int32_t s : large)
@@ -89,13 +94,18 @@ static void build_schedule(Pencil& P) {
       sp.nfronts = act;
       align2();
       sp.trsm_off = (int32_t)sched.size();
+      std::vector<int32_t> tpre(1, 0);
       for (int32_t q = 0; q < act; q++) {
         int32_t s = large[q];
         int64_t ns = S.ns(s), nf = S.nf(s);
         int64_t k0 = t * kNB, kb = std::min<int64_t>(kNB, ns - k0);
         for (int64_t r = k0 + kb; r < nf; r += kTrsmRows) { sched.push_back(s); sched.push_back((int32_t)r); }
+        tpre.push_back((int32_t)((sched.size() - sp.trsm_off) / 2));
       }
       sp.trsm_cnt = (int32_t)((sched.size() - sp.trsm_off) / 2);
+      sp.trsm_prefix_off = (int32_t)sched.size();
+      sched.insert(sched.end(), tpre.begin(), tpre.end());
+      P.splan.partial_size = std::max<int64_t>(P.splan.partial_size, (int64_t)sp.trsm_cnt * kNB);
       sp.prefix_off = (int32_t)sched.size();
       int64_t tot = 0;
       for (int32_t q = 0; q < act; q++) {
@@ -114,21 +124,39 @@ static void build_schedule(Pencil& P) {
       lp.steps.push_back(sp);
     }
   }
-  // solve plan: all fronts by level
-  std::vector<int32_t> sfronts;
-  P.splan.level_off.clear();
-  P.splan.level_cnt.clear();
+  // solve plan: small fronts reuse the factorization lists; large fronts get
+  // gather tasks of kSolveChunk rows and reuse the panel tasks of each step
+  P.splan.levels.assign(S.nlevels, SolveLevel());
   for (int64_t L = 0; L < S.nlevels; L++) {
-    P.splan.level_off.push_back((int32_t)(sched.size() + sfronts.size()));
-    P.splan.level_cnt.push_back((int32_t)bylevel[L].size());
-    sfronts.insert(sfronts.end(), bylevel[L].begin(), bylevel[L].end());
+    const LevelPlan& lp = P.levels[L];
+    SolveLevel& sl = P.splan.levels[L];
+    sl.small_off = lp.small_off;
+    sl.small_cnt = lp.small_cnt;
+    sl.large_off = lp.large_off;
+    sl.large_cnt = lp.large_cnt;
+    align2();
+    sl.init_off = (int32_t)sched.size();
+    for (int32_t q = 0; q < lp.large_cnt; q++) {
+      int32_t s = sched[lp.large_off + q];
+      for (int64_t r = 0; r < S.nf(s); r += kSolveChunk) { sched.push_back(s); sched.push_back((int32_t)r); }
+    }
+    sl.init_cnt = (int32_t)((sched.size() - sl.init_off) / 2);
+    for (const StepPlan& sp : lp.steps) {
+      SolveStep ss;
+      ss.t = sp.t;
+      ss.nfronts = sp.nfronts;
+      ss.task_off = sp.trsm_off;
+      ss.task_cnt = sp.trsm_cnt;
+      ss.prefix_off = sp.trsm_prefix_off;
+      sl.steps.push_back(ss);
+    }
   }
-  sched.insert(sched.end(), sfronts.begin(), sfronts.end());
   Ctx* c = P.ctx;
   P.d_sched.upload(c, sched);
   P.d_wptr.upload(c, wptr);
+  P.d_tptr.upload(c, tptr);
   P.d_tilew.upload(c, tilew);
-  P.splan.fronts = P.d_sched.get();
+  P.splan.sched = P.d_sched.get();
 }
 
 void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
@@ -184,8 +212,10 @@ void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const in
   P.meta.asrc = P.d_asrc.get();
   P.meta.adst = P.d_adst.get();
   P.meta.tilew = P.d_tilew.get();
+  P.meta.tptr = P.d_tptr.get();
   P.U.alloc(ctx, (size_t)S.pool_size);
   P.W.alloc(ctx, (size_t)P.wsize);
+  P.Tinv.alloc(ctx, (size_t)std::max<int64_t>(P.tsize, 1));
   P.sig.alloc(ctx, 8);
   P.scratch.reset(new NumFactor());
   factor_alloc(P, *P.scratch);
@@ -240,9 +270,10 @@ void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b) {
                       bv, P.sig.get(), F.L.get(), P.U.get(), st);
     for (const StepPlan& sp : lp.steps) {
       launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, F.L.get(), F.D.get(),
-                         F.E.get(), F.tperm.get(), F.stats.get(), st);
+                         F.E.get(), F.tperm.get(), P.Tinv.get(), F.stats.get(), st);
       launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm_off), sp.trsm_cnt, sp.t,
-                        F.L.get(), P.W.get(), F.D.get(), F.E.get(), F.tperm.get(), F.stats.get(), st);
+                        F.L.get(), P.W.get(), F.D.get(), F.E.get(), F.tperm.get(), P.Tinv.get(),
+                        F.stats.get(), st);
       launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles, sp.t,
                    F.L.get(), P.U.get(), P.W.get(), st);
     }
@@ -265,9 +296,11 @@ void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x) {
     F.xe.alloc(c, (size_t)P.n);
     F.ye.alloc(c, (size_t)P.n);
     F.R.alloc(c, P.S.rows.size());
+    F.partial.alloc(c, (size_t)P.splan.partial_size);
   }
   solve_enqueue<double>(P.splan, P.meta, F.L.get(), F.D.get(), F.E.get(), F.tperm.get(),
-                        P.d_perm.get(), P.n, b, x, F.xe.get(), F.ye.get(), F.R.get(), c->stream);
+                        P.d_perm.get(), P.n, b, x, F.xe.get(), F.ye.get(), F.R.get(),
+                        F.partial.get(), c->stream);
 }
 
 }  // namespace kth

@@ -81,6 +81,7 @@ struct StepPlan {
   int32_t t;
   int32_t nfronts;     // active large fronts (prefix of the level's sorted list)
   int32_t trsm_off, trsm_cnt;   // Int2 tasks (offset in int32 units)
+  int32_t trsm_prefix_off;      // [nfronts+1] task ranges per active front
   int32_t prefix_off, ntiles;   // tile prefix over active fronts
 };
 
@@ -105,14 +106,16 @@ struct Pencil {
   DBuf<int32_t> col;
   DBuf<double> aval, bval, zeros;
   // device metadata
-  DBuf<int64_t> d_sfirst, d_rptr, d_lptr, d_uptr, d_wptr, d_eptr, d_cptr, d_acptr, d_asrc, d_adst,
-      d_perm;
+  DBuf<int64_t> d_sfirst, d_rptr, d_lptr, d_uptr, d_wptr, d_tptr, d_eptr, d_cptr, d_acptr, d_asrc,
+      d_adst, d_perm;
   DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched;
   FrontMeta meta{};
   std::vector<LevelPlan> levels;
   SolvePlan splan;
   int64_t wsize = 0;   // workspace doubles
+  int64_t tsize = 0;   // tile-inverse doubles
   DBuf<double> U, W;   // update-block pool, panel workspace
+  DBuf<double> Tinv;   // inverses of the current pivot tiles
   DBuf<double> sig;    // device scalars: [0] sigma of the running factorization
   std::unique_ptr<NumFactor> scratch;   // factor reused by inertia-only calls
   double flops() const { return S.flops; }
@@ -128,7 +131,7 @@ struct NumFactor {
   FactStats hs{};
   bool have_stats = false;
   // solve scratch
-  DBuf<double> xe, ye, R;
+  DBuf<double> xe, ye, R, partial;
 };
 
 void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,

@@ -352,10 +352,10 @@ __global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* task
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* fronts, int t,
                                                     double* L, double* D, double* E,
-                                                    int32_t* tperm, FactStats* st) {
+                                                    int32_t* tperm, double* tinv, FactStats* st) {
   __shared__ double T[kNB * kNB];
-  __shared__ double sv[NT / 64];
-  __shared__ int si[NT / 64];
+  __shared__ double sv[(NT + 63) / 64];
+  __shared__ int si[(NT + 63) / 64];
   __shared__ int lp[kNB];
   __shared__ double dd[kNB], ee[kNB];
   __shared__ double lcol[2 * kNB];
@@ -383,12 +383,30 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
     E[f0 + k0 + q] = ee[q];
     tperm[f0 + k0 + q] = lp[q];
   }
+  // inverse of the unit-lower tile factor, column c by lane c (zero-padded to kNB)
+  double* Ti = tinv + M.tptr[s];
+  for (int c = tid; c < kNB; c += NT) {
+    for (int r = 0; r < kNB; r++) {
+      double x;
+      if (r < c || r >= kb || c >= kb) x = (r == c) ? 1.0 : 0.0;
+      else if (r == c) x = 1.0;
+      else {
+        x = 0.0;
+        for (int p = c; p < r; p++) x -= T[r + p * kb] * Ti[p + (int64_t)c * kNB];
+      }
+      Ti[r + (int64_t)c * kNB] = x;
+    }
+  }
   if (tid == 0) flush_counts(cnt, st);
 }
 
+typedef double double4v __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------------------
-// Large fronts: rows below pivot tile t.  For row i: s = S(i, k0 + perm[.]),
-// w = s L_tt^{-T}, l = w D^{-1}; panel row <- l, workspace W row <- w.
+// Large fronts: rows below pivot tile t, 64 rows per workgroup.
+//   W = S P^T L_tt^{-T}  (MFMA, with the tile inverse from k_tile_factor)
+//   L21 = W D^{-1}       (1x1 / 2x2 blocks)
+// The panel rows receive L21, the workspace receives W (= L21 D).
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* tasks, int t,
@@ -396,13 +414,15 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
                                                    const double* __restrict__ D,
                                                    const double* __restrict__ E,
                                                    const int32_t* __restrict__ tperm,
+                                                   const double* __restrict__ tinv,
                                                    FactStats* st) {
-  __shared__ double Lt[kNB * kNB];
+  __shared__ double As[kTile * kNB];   // S' rows x k, ld kTile; reused for W
+  __shared__ double Bs[kNB * kNB];     // Linv(q, p) at q + p*kNB
   __shared__ double dd[kNB], ee[kNB];
   __shared__ int pp[kNB];
   __shared__ double sv[NT / 64];
   const Int2 tk = tasks[blockIdx.x];
-  const int s = tk.a;
+  const int s = tk.a, r0 = tk.b;
   const int tid = threadIdx.x;
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
@@ -411,53 +431,67 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
   const int kb = min(kNB, ns - k0);
   double* Lp = L + M.lptr[s];
   double* Wp = W + M.wptr[s];
-  for (int x = tid; x < kNB * kNB; x += NT) {
-    const int i = x % kNB, j = x / kNB;
-    Lt[x] = (i < kb && j < kb && i > j) ? Lp[(k0 + i) + (int64_t)(k0 + j) * nf] : 0.0;
-  }
+  const double* Ti = tinv + M.tptr[s];
   for (int q = tid; q < kNB; q += NT) {
     dd[q] = q < kb ? D[f0 + k0 + q] : 1.0;
     ee[q] = q < kb ? E[f0 + k0 + q] : 0.0;
     pp[q] = q < kb ? tperm[f0 + k0 + q] : 0;
   }
+  for (int x = tid; x < kNB * kNB; x += NT) Bs[x] = Ti[x];
   __syncthreads();
-  const int i = tk.b + tid;
+  const int nr = min(kTile, nf - r0);
+  for (int x = tid; x < kTile * kNB; x += NT) {
+    const int r = x % kTile, q = x / kTile;
+    As[x] = (r < nr && q < kb) ? Lp[(r0 + r) + (int64_t)(k0 + pp[q]) * nf] : 0.0;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  double4v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) acc[a][b] = (double4v){0.0, 0.0, 0.0, 0.0};
+  const int m = lane & 15, kk = lane >> 4;
+  for (int q0 = 0; q0 < kNB; q0 += 4) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; a++) av[a] = As[(wr + a * 16 + m) + (q0 + kk) * kTile];
+#pragma unroll
+    for (int b = 0; b < 2; b++) bv[b] = Bs[(wc + b * 16 + m) + (q0 + kk) * kNB];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+  __syncthreads();   // everyone is done reading As
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+        As[(wr + a * 16 + 4 * r + (lane >> 4)) + (wc + b * 16 + (lane & 15)) * kTile] = acc[a][b][r];
+  __syncthreads();
   double maxl = 0.0;
-  if (i < nf) {
-    double w[kNB];
-#pragma unroll
-    for (int q = 0; q < kNB; q++) w[q] = q < kb ? Lp[i + (int64_t)(k0 + pp[q]) * nf] : 0.0;
-    // w L_tt^T = s  (L_tt unit lower)
-#pragma unroll
-    for (int p = 0; p < kNB; p++) {
-      const double wp = w[p];
-#pragma unroll
-      for (int q = p + 1; q < kNB; q++) w[q] -= Lt[q + p * kNB] * wp;
+  for (int x = tid; x < kTile * kNB; x += NT) {
+    const int r = x % kTile, q = x / kTile;
+    if (r >= nr || q >= kb) continue;
+    const double wq = As[r + q * kTile];
+    double l;
+    if (q + 1 < kb && ee[q] != 0.0) {            // first row of a 2x2 block
+      const double a = dd[q], b = ee[q], c = dd[q + 1], det = a * c - b * b;
+      l = (c * wq - b * As[r + (q + 1) * kTile]) / det;
+    } else if (q > 0 && ee[q - 1] != 0.0) {      // second row of a 2x2 block
+      const double a = dd[q - 1], b = ee[q - 1], c = dd[q], det = a * c - b * b;
+      l = (a * wq - b * As[r + (q - 1) * kTile]) / det;
+    } else {
+      l = dd[q] != 0.0 ? wq / dd[q] : 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < kNB; q++) {
-      if (q < kb) {
-        Wp[i + (int64_t)q * nf] = w[q];
-      }
-    }
-    // l = w D^{-1}
-#pragma unroll
-    for (int q = 0; q < kNB; q++) {
-      if (q < kb) {
-        double l;
-        if (q + 1 < kNB && ee[q] != 0.0) {   // 2x2 block (q, q+1)
-          const double a = dd[q], b = ee[q], c = dd[q + 1], det = a * c - b * b;
-          l = (c * w[q] - b * w[q + 1]) / det;
-        } else if (q > 0 && ee[q - 1] != 0.0) {  // second row of a 2x2 block
-          const double a = dd[q - 1], b = ee[q - 1], c = dd[q], det = a * c - b * b;
-          l = (a * w[q] - b * w[q - 1]) / det;
-        } else {
-          l = dd[q] != 0.0 ? w[q] / dd[q] : 0.0;
-        }
-        Lp[i + (int64_t)(k0 + q) * nf] = l;
-        maxl = fmax(maxl, fabs(l));
-      }
-    }
+    Lp[(r0 + r) + (int64_t)(k0 + q) * nf] = l;
+    Wp[(r0 + r) + (int64_t)q * nf] = wq;
+    maxl = fmax(maxl, fabs(l));
   }
   maxl = block_max<NT>(maxl, sv);
   if (tid == 0) atomicMax(&st->max_l_bits, dbits(maxl));
@@ -468,8 +502,6 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
 // The trailing range [r0, nf) is cut into 64-chunks aligned at ns (so no chunk
 // mixes panel and update-block columns); one workgroup per lower tile (bi >= bj).
 // ---------------------------------------------------------------------------
-typedef double double4v __attribute__((ext_vector_type(4)));
-
 __device__ inline void chunk_range(int c, int r0, int ns, int nf, int nc1, int& b, int& e) {
   if (c < nc1) { b = r0 + c * kTile; e = min(b + kTile, ns); }
   else { b = ns + (c - nc1) * kTile; e = min(b + kTile, nf); }
@@ -594,19 +626,19 @@ void launch_front_init(const FrontMeta& M, const Int2* tasks, int32_t count, con
 }
 
 void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t t,
-                        double* L, double* D, double* E, int32_t* tperm, FactStats* st,
-                        hipStream_t s) {
+                        double* L, double* D, double* E, int32_t* tperm, double* tinv,
+                        FactStats* st, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_tile_factor<256>, dim3(count), dim3(256), 0, s, M, fronts, t, L, D, E,
-                     tperm, st);
+  hipLaunchKernelGGL(k_tile_factor<64>, dim3(count), dim3(64), 0, s, M, fronts, t, L, D, E, tperm,
+                     tinv, st);
 }
 
 void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, double* L,
                        double* W, const double* D, const double* E, const int32_t* tperm,
-                       FactStats* st, hipStream_t s) {
+                       const double* tinv, FactStats* st, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_panel_trsm<kTrsmRows>, dim3(count), dim3(kTrsmRows), 0, s, M, tasks, t, L,
-                     W, D, E, tperm, st);
+  hipLaunchKernelGGL(k_panel_trsm<256>, dim3(count), dim3(256), 0, s, M, tasks, t, L, W, D, E,
+                     tperm, tinv, st);
 }
 
 void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,

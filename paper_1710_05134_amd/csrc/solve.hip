@@ -143,6 +143,168 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(FrontMeta M, const int32_t* fr
   }
 }
 
+// ---- large fronts (tile width kNB), level-batched tile steps ----------------
+
+// R_s <- [xe(cols); 0] + children's update vectors, rows [r0, r0 + kSolveChunk)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_lfwd_init(FrontMeta M, const Int2* tasks,
+                                                  const double* __restrict__ xe, double* R) {
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a, r0 = tk.b;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int r1 = min(r0 + kSolveChunk, nf);
+  double* Rs = R + M.rptr[s];
+  for (int i = r0 + (int)threadIdx.x; i < r1; i += NT) Rs[i] = i < ns ? xe[f0 + i] : 0.0;
+  __syncthreads();
+  for (int64_t q = M.cptr[s]; q < M.cptr[s + 1]; q++) {
+    const int c = M.clist[q];
+    const int nsc = (int)(M.sfirst[c + 1] - M.sfirst[c]);
+    const int nuc = (int)(M.rptr[c + 1] - M.rptr[c]) - nsc;
+    const double* Rc = R + M.rptr[c] + nsc;
+    const int32_t* map = M.emap + M.eptr[c];
+    int lo = 0, hi = nuc;
+    while (lo < hi) { int mid = (lo + hi) >> 1; if (map[mid] < r0) lo = mid + 1; else hi = mid; }
+    const int a0 = lo;
+    hi = nuc;
+    while (lo < hi) { int mid = (lo + hi) >> 1; if (map[mid] < r1) lo = mid + 1; else hi = mid; }
+    for (int a = a0 + (int)threadIdx.x; a < lo; a += NT) Rs[map[a]] += Rc[a];
+    __syncthreads();
+  }
+}
+
+// one wavefront per front: z = P_t r_t, L_tt z = P_t r_t, written back in place
+template <typename T>
+__global__ __launch_bounds__(64) void k_lfwd_tile(FrontMeta M, const int32_t* fronts, int t,
+                                                  const T* L, const int32_t* __restrict__ tperm,
+                                                  double* R) {
+  const int s = fronts[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB, kb = min(kNB, ns - k0);
+  const T* Lp = L + M.lptr[s];
+  double* Rs = R + M.rptr[s];
+  double z = lane < kb ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
+  for (int p = 0; p < kb; p++) {
+    const double zp = __shfl(z, p);
+    if (lane > p && lane < kb) z -= (double)Lp[(k0 + lane) + (int64_t)(k0 + p) * nf] * zp;
+  }
+  if (lane < kb) Rs[k0 + lane] = z;
+}
+
+// rows [r0, r0 + kTrsmRows) below tile t: R_i -= sum_q L(i, k0+q) z_q
+template <typename T>
+__global__ __launch_bounds__(64) void k_lfwd_gemv(FrontMeta M, const Int2* tasks, int t,
+                                                  const T* L, double* R) {
+  __shared__ double z[kNB];
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a, r0 = tk.b;
+  const int lane = threadIdx.x;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB, kb = min(kNB, ns - k0);
+  const T* Lp = L + M.lptr[s];
+  double* Rs = R + M.rptr[s];
+  z[lane] = lane < kb ? Rs[k0 + lane] : 0.0;
+  __syncthreads();
+  const int i = r0 + lane;
+  if (i < nf) {
+    double acc = 0.0;
+    for (int q = 0; q < kb; q++) acc += (double)Lp[i + (int64_t)(k0 + q) * nf] * z[q];
+    Rs[i] -= acc;
+  }
+}
+
+// y = D^{-1} z for the fully-summed rows of large fronts
+__global__ __launch_bounds__(NT) void k_ldiag(FrontMeta M, const int32_t* fronts,
+                                              const double* __restrict__ D,
+                                              const double* __restrict__ E,
+                                              const double* __restrict__ R, double* ye) {
+  const int s = fronts[blockIdx.x];
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const double* Rs = R + M.rptr[s];
+  for (int q = threadIdx.x; q < ns; q += NT) {
+    const int64_t k = f0 + q;
+    double y;
+    if (q + 1 < ns && E[k] != 0.0) {
+      const double a = D[k], b = E[k], c = D[k + 1], det = a * c - b * b;
+      y = (c * Rs[q] - b * Rs[q + 1]) / det;
+    } else if (q > 0 && E[k - 1] != 0.0 && (q % kNB) != 0) {
+      const double a = D[k - 1], b = E[k - 1], c = D[k], det = a * c - b * b;
+      y = (a * Rs[q] - b * Rs[q - 1]) / det;
+    } else {
+      y = D[k] != 0.0 ? Rs[q] / D[k] : 0.0;
+    }
+    ye[k] = y;
+  }
+}
+
+// backward: partial[task * kNB + q] = sum over the task's rows i of L(i, k0+q) x(rows[i])
+template <typename T>
+__global__ __launch_bounds__(64) void k_lbwd_gemv(FrontMeta M, const Int2* tasks, int t,
+                                                  const T* L, const double* __restrict__ xe,
+                                                  double* partial) {
+  __shared__ double xv[kTrsmRows];
+  __shared__ double prod[(kTrsmRows + 1) * kNB];
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a, r0 = tk.b;
+  const int lane = threadIdx.x;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB, kb = min(kNB, ns - k0);
+  const int nr = min(kTrsmRows, nf - r0);
+  const T* Lp = L + M.lptr[s];
+  const int32_t* rows = M.rows + M.rptr[s];
+  for (int r = lane; r < kTrsmRows; r += 64) xv[r] = r < nr ? xe[rows[r0 + r]] : 0.0;
+  __syncthreads();
+  // products staged so that every global load is coalesced (lanes over rows)
+  for (int q = 0; q < kb; q++)
+    for (int r = lane; r < kTrsmRows; r += 64)
+      prod[r + q * (kTrsmRows + 1)] =
+          r < nr ? (double)Lp[(r0 + r) + (int64_t)(k0 + q) * nf] * xv[r] : 0.0;
+  __syncthreads();
+  double acc = 0.0;
+  if (lane < kb)
+    for (int r = 0; r < nr; r++) acc += prod[r + lane * (kTrsmRows + 1)];
+  partial[(int64_t)blockIdx.x * kNB + lane] = acc;
+}
+
+// one wavefront per front: g = y - sum of partials (task order), L_tt^T w = g,
+// x(f0 + k0 + perm[q]) = w_q
+template <typename T>
+__global__ __launch_bounds__(64) void k_lbwd_tile(FrontMeta M, const int32_t* fronts,
+                                                  const int32_t* task_prefix, int t, const T* L,
+                                                  const int32_t* __restrict__ tperm,
+                                                  const double* __restrict__ ye,
+                                                  const double* __restrict__ partial, double* xe) {
+  const int s = fronts[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB, kb = min(kNB, ns - k0);
+  const T* Lp = L + M.lptr[s];
+  double g = 0.0;
+  if (lane < kb) {
+    double acc = 0.0;
+    for (int q = task_prefix[blockIdx.x]; q < task_prefix[blockIdx.x + 1]; q++)
+      acc += partial[(int64_t)q * kNB + lane];
+    g = ye[f0 + k0 + lane] - acc;
+  }
+  for (int p = kb - 1; p >= 0; p--) {
+    const double wp = __shfl(g, p);
+    if (lane < p) g -= (double)Lp[(k0 + p) + (int64_t)(k0 + lane) * nf] * wp;
+  }
+  if (lane < kb) xe[f0 + k0 + tperm[f0 + k0 + lane]] = g;
+  (void)nf;
+}
+
 __global__ void k_gather(int64_t n, const int64_t* __restrict__ perm, const double* __restrict__ x,
                          double* __restrict__ xe) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
@@ -167,28 +329,50 @@ inline int grid_for(int64_t n) {
 template <typename T>
 void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const double* D,
                    const double* E, const int32_t* tperm, const int64_t* perm, int64_t n,
-                   const double* b, double* x, double* xe, double* ye, double* R, hipStream_t s) {
+                   const double* b, double* x, double* xe, double* ye, double* R, double* partial,
+                   hipStream_t s) {
+  const int32_t* sc = P.sched;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(256), 0, s, n, perm, b, xe);
-  for (size_t l = 0; l < P.level_off.size(); l++) {
-    const int cnt = P.level_cnt[l];
-    if (cnt > 0)
-      hipLaunchKernelGGL((k_solve_fwd<T>), dim3(cnt), dim3(NT), 0, s, M, P.fronts + P.level_off[l],
+  for (const SolveLevel& lv : P.levels) {
+    if (lv.small_cnt > 0)
+      hipLaunchKernelGGL((k_solve_fwd<T>), dim3(lv.small_cnt), dim3(NT), 0, s, M, sc + lv.small_off,
                          L, D, E, tperm, xe, R, ye);
+    if (lv.large_cnt == 0) continue;
+    hipLaunchKernelGGL((k_lfwd_init<T>), dim3(lv.init_cnt), dim3(NT), 0, s, M,
+                       reinterpret_cast<const Int2*>(sc + lv.init_off), xe, R);
+    for (const SolveStep& st : lv.steps) {
+      hipLaunchKernelGGL((k_lfwd_tile<T>), dim3(st.nfronts), dim3(64), 0, s, M, sc + lv.large_off,
+                         st.t, L, tperm, R);
+      if (st.task_cnt > 0)
+        hipLaunchKernelGGL((k_lfwd_gemv<T>), dim3(st.task_cnt), dim3(64), 0, s, M,
+                           reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, R);
+    }
+    hipLaunchKernelGGL(k_ldiag, dim3(lv.large_cnt), dim3(NT), 0, s, M, sc + lv.large_off, D, E, R, ye);
   }
-  for (size_t l = P.level_off.size(); l-- > 0;) {
-    const int cnt = P.level_cnt[l];
-    if (cnt > 0)
-      hipLaunchKernelGGL((k_solve_bwd<T>), dim3(cnt), dim3(NT), 0, s, M, P.fronts + P.level_off[l],
+  for (size_t l = P.levels.size(); l-- > 0;) {
+    const SolveLevel& lv = P.levels[l];
+    if (lv.small_cnt > 0)
+      hipLaunchKernelGGL((k_solve_bwd<T>), dim3(lv.small_cnt), dim3(NT), 0, s, M, sc + lv.small_off,
                          L, tperm, ye, xe);
+    for (size_t q = lv.steps.size(); q-- > 0;) {
+      const SolveStep& st = lv.steps[q];
+      if (st.task_cnt > 0)
+        hipLaunchKernelGGL((k_lbwd_gemv<T>), dim3(st.task_cnt), dim3(64), 0, s, M,
+                           reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, xe, partial);
+      hipLaunchKernelGGL((k_lbwd_tile<T>), dim3(st.nfronts), dim3(64), 0, s, M, sc + lv.large_off,
+                         sc + st.prefix_off, st.t, L, tperm, ye, partial, xe);
+    }
   }
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, s, n, perm, xe, x);
 }
 
 template void solve_enqueue<double>(const SolvePlan&, const FrontMeta&, const double*, const double*,
                                     const double*, const int32_t*, const int64_t*, int64_t,
-                                    const double*, double*, double*, double*, double*, hipStream_t);
+                                    const double*, double*, double*, double*, double*, double*,
+                                    hipStream_t);
 template void solve_enqueue<float>(const SolvePlan&, const FrontMeta&, const float*, const double*,
                                    const double*, const int32_t*, const int64_t*, int64_t,
-                                   const double*, double*, double*, double*, double*, hipStream_t);
+                                   const double*, double*, double*, double*, double*, double*,
+                                   hipStream_t);
 
 }  // namespace kth

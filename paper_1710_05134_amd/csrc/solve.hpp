@@ -9,17 +9,33 @@
 
 namespace kth {
 
+struct SolveStep {
+  int32_t t;
+  int32_t nfronts;               // active large fronts (prefix of the level's list)
+  int32_t task_off, task_cnt;    // Int2 (front, row) tasks of kTrsmRows rows below the tile
+  int32_t prefix_off;            // [nfronts+1] task ranges per active front
+};
+
+struct SolveLevel {
+  int32_t small_off = 0, small_cnt = 0;   // fronts solved by one workgroup each
+  int32_t large_off = 0, large_cnt = 0;   // large fronts (sorted by ns, descending)
+  int32_t init_off = 0, init_cnt = 0;     // Int2 (front, row) tasks of the gather step
+  std::vector<SolveStep> steps;
+};
+
 struct SolvePlan {
-  const int32_t* fronts = nullptr;   // device: all fronts grouped by level
-  std::vector<int32_t> level_off;    // offset of each level's group
-  std::vector<int32_t> level_cnt;
+  const int32_t* sched = nullptr;    // device int32 schedule array
+  std::vector<SolveLevel> levels;
+  int64_t partial_size = 1;          // doubles for the backward partial sums
 };
 
 // x = (A - sigma B)^{-1} b with a kept factor (T = double or float panels).
-// xe, ye: n-vectors of scratch; R: work vectors (rows.size() doubles).
+// xe, ye: n-vectors of scratch; R: work vectors (rows.size() doubles);
+// partial: P.partial_size doubles.
 template <typename T>
 void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const double* D,
                    const double* E, const int32_t* tperm, const int64_t* perm, int64_t n,
-                   const double* b, double* x, double* xe, double* ye, double* R, hipStream_t s);
+                   const double* b, double* x, double* xe, double* ye, double* R, double* partial,
+                   hipStream_t s);
 
 }  // namespace kth
