@@ -35,6 +35,7 @@ __device__ inline void block_argmax(double& v, int& idx, double* sv, int* si) {
     int oi = __shfl_xor(idx, off);
     if (ov > v || (ov == v && oi >= 0 && (idx < 0 || oi < idx))) { v = ov; idx = oi; }
   }
+  if constexpr (NT == 64) return;   // one wavefront: every lane already holds the result
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) { sv[wave] = v; si[wave] = idx; }
   __syncthreads();
@@ -54,6 +55,7 @@ __device__ inline void block_argmax(double& v, int& idx, double* sv, int* si) {
 template <int NT>
 __device__ inline double block_max(double v, double* sv) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if constexpr (NT == 64) return v;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) sv[wave] = v;
   __syncthreads();
@@ -102,16 +104,34 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
   __syncthreads();
   int k = 0;
   while (k < ncand) {
-    // gamma_1 = max_{k < i < ncand} |F(i,k)|
-    double v = -1.0;
-    int idx = -1;
-    for (int i = k + 1 + tid; i < ncand; i += NT) {
-      double x = fabs(F[i + k * ld]);
-      if (x > v) { v = x; idx = i; }
+    // gamma_1 = max_{k < i < ncand} |F(i,k)|, argmax r (ties: smallest row)
+    int r;
+    double g1;
+    if constexpr (NT == 64) {
+      // one wavefront: a single 64-bit max over keys |x| (low 8 mantissa bits replaced by
+      // 128 - row, so ties go to the smaller row; key 0 = no candidate)
+      unsigned long long key = 0;
+      for (int i = k + 1 + tid; i < ncand; i += NT) {
+        unsigned long long kk2 = (dbits(fabs(F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
+        key = kk2 > key ? kk2 : key;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(key, off);
+        key = o > key ? o : key;
+      }
+      if (key == 0) { r = k; g1 = 0.0; }
+      else { r = 128 - (int)(key & 0xFFull); g1 = fabs(F[r + k * ld]); }
+    } else {
+      double v = -1.0;
+      int idx = -1;
+      for (int i = k + 1 + tid; i < ncand; i += NT) {
+        double x = fabs(F[i + k * ld]);
+        if (x > v) { v = x; idx = i; }
+      }
+      block_argmax<NT>(v, idx, sv, si);
+      g1 = idx < 0 ? 0.0 : v;
+      r = idx < 0 ? k : idx;
     }
-    block_argmax<NT>(v, idx, sv, si);
-    const double g1 = idx < 0 ? 0.0 : v;
-    const int r = idx < 0 ? k : idx;
     const double akk = fabs(F[k + k * ld]);
     int kind = 0;  // 0: 1x1 at k; 1: 1x1 at r (swap k,r); 2: 2x2 (k, r -> k+1)
     if (!(g1 == 0.0 || akk >= kAlphaBK * g1)) {
@@ -146,9 +166,39 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
       if (dk != 0.0) {
         for (int i = k + 1 + tid; i < nrows; i += NT) lcol[i] = F[i + k * ld] / dk;
         __syncthreads();
-        for (int j = k + 1 + wave; j < nrows; j += NW) {
-          const double fj = F[j + k * ld];
-          for (int i = j + lane; i < nrows; i += 64) F[i + j * ld] -= lcol[i] * fj;
+        if constexpr (NT == 64) {
+          // lane owns row i: F(i, j) -= l_i F(j, k) for k < j <= i; loads of the next
+          // group are issued before the stores of the current one (no aliasing: other j)
+          const int i = lane;
+          if (i > k && i < nrows) {
+            const double li = lcol[i];
+            int j = k + 1;
+            if (j + 3 <= i) {
+              double c0 = F[j + k * ld], c1 = F[j + 1 + k * ld], c2 = F[j + 2 + k * ld], c3 = F[j + 3 + k * ld];
+              double a0 = F[i + j * ld], a1 = F[i + (j + 1) * ld], a2 = F[i + (j + 2) * ld], a3 = F[i + (j + 3) * ld];
+              for (;;) {
+                const double r0 = a0 - li * c0, r1 = a1 - li * c1, r2 = a2 - li * c2, r3 = a3 - li * c3;
+                const int jn = j + 4;
+                const bool more = jn + 3 <= i;
+                if (more) {
+                  c0 = F[jn + k * ld]; c1 = F[jn + 1 + k * ld]; c2 = F[jn + 2 + k * ld]; c3 = F[jn + 3 + k * ld];
+                  a0 = F[i + jn * ld]; a1 = F[i + (jn + 1) * ld]; a2 = F[i + (jn + 2) * ld]; a3 = F[i + (jn + 3) * ld];
+                }
+                F[i + j * ld] = r0;
+                F[i + (j + 1) * ld] = r1;
+                F[i + (j + 2) * ld] = r2;
+                F[i + (j + 3) * ld] = r3;
+                j = jn;
+                if (!more) break;
+              }
+            }
+            for (; j <= i; j++) F[i + j * ld] -= li * F[j + k * ld];
+          }
+        } else {
+          for (int j = k + 1 + wave; j < nrows; j += NW) {
+            const double fj = F[j + k * ld];
+            for (int i = j + lane; i < nrows; i += 64) F[i + j * ld] -= lcol[i] * fj;
+          }
         }
         __syncthreads();
         for (int i = k + 1 + tid; i < nrows; i += NT) {
@@ -181,9 +231,25 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
         lcol2[i] = (a * w2 - b * w1) / det;
       }
       __syncthreads();
-      for (int j = k + 2 + wave; j < nrows; j += NW) {
-        const double w1 = F[j + k * ld], w2 = F[j + (k + 1) * ld];
-        for (int i = j + lane; i < nrows; i += 64) F[i + j * ld] -= lcol[i] * w1 + lcol2[i] * w2;
+      if constexpr (NT == 64) {
+        const int i = lane;
+        if (i > k + 1 && i < nrows) {
+          const double l1 = lcol[i], l2 = lcol2[i];
+          int j = k + 2;
+          for (; j + 1 <= i; j += 2) {
+            const double w10 = F[j + k * ld], w20 = F[j + (k + 1) * ld];
+            const double w11 = F[j + 1 + k * ld], w21 = F[j + 1 + (k + 1) * ld];
+            const double a0 = F[i + j * ld], a1 = F[i + (j + 1) * ld];
+            F[i + j * ld] = a0 - (l1 * w10 + l2 * w20);
+            F[i + (j + 1) * ld] = a1 - (l1 * w11 + l2 * w21);
+          }
+          for (; j <= i; j++) F[i + j * ld] -= l1 * F[j + k * ld] + l2 * F[j + (k + 1) * ld];
+        }
+      } else {
+        for (int j = k + 2 + wave; j < nrows; j += NW) {
+          const double w1 = F[j + k * ld], w2 = F[j + (k + 1) * ld];
+          for (int i = j + lane; i < nrows; i += 64) F[i + j * ld] -= lcol[i] * w1 + lcol2[i] * w2;
+        }
       }
       __syncthreads();
       for (int i = k + 2 + tid; i < nrows; i += NT) {
@@ -198,6 +264,118 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
   }
   maxl = block_max<NT>(maxl, sv);
   if (tid == 0) cnt.maxl = fmax(cnt.maxl, maxl);
+}
+
+// Bunch-Kaufman LDL^T of one kb x kb pivot tile (kb <= kNB) in LDS, by 4 wavefronts:
+// wave 0 searches pivots (lanes = rows, shuffle reductions), every wave updates a
+// quarter of the columns of each row (lane = row, wave = column residue mod 4).
+__device__ void bk_tile_lds(double* F, int ld, int kb, int* lp, double* d, double* e,
+                            double* lcol, BKCounts& cnt, int* dec) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double maxl = 0.0;
+  if (tid < kNB) lp[tid] = tid;
+  __syncthreads();
+  int k = 0;
+  while (k < kb) {
+    if (wave == 0) {
+      // gamma_1 and its row r among the candidates k < i < kb (ties: smallest row)
+      unsigned long long key = 0;
+      const int i = lane;
+      if (i > k && i < kb)
+        key = (dbits(fabs(F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
+      for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(key, off);
+        key = o > key ? o : key;
+      }
+      const int r = key == 0 ? k : 128 - (int)(key & 0xFFull);
+      const double g1 = key == 0 ? 0.0 : fabs(F[r + k * ld]);
+      const double akk = fabs(F[k + k * ld]);
+      int kind = 0;
+      if (!(g1 == 0.0 || akk >= kAlphaBK * g1)) {
+        double gv = 0.0;
+        if (i >= k && i < kb && i != r) gv = i < r ? fabs(F[r + i * ld]) : fabs(F[i + r * ld]);
+        for (int off = 32; off > 0; off >>= 1) gv = fmax(gv, __shfl_xor(gv, off));
+        if (akk * gv >= kAlphaBK * g1 * g1) kind = 0;
+        else if (fabs(F[r + r * ld]) >= kAlphaBK * gv) kind = 1;
+        else kind = 2;
+      }
+      if (lane == 0) { dec[0] = kind; dec[1] = r; }
+    }
+    __syncthreads();
+    const int kind = dec[0], r = dec[1];
+    if (kind == 1 || (kind == 2 && r != k + 1)) {
+      const int a = kind == 1 ? k : k + 1;
+      lds_sym_swap<256>(F, ld, kb, a, r);
+      if (tid == 0) { int t = lp[a]; lp[a] = lp[r]; lp[r] = t; }
+      __syncthreads();
+    }
+    if (kind < 2) {
+      const double dk = F[k + k * ld];
+      if (tid == 0) {
+        d[k] = dk; e[k] = 0.0;
+        if (dk < 0) cnt.neg++; else if (dk > 0) cnt.pos++; else cnt.zero++;
+        cnt.mind = fmin(cnt.mind, fabs(dk));
+      }
+      if (wave == 0 && lane > k && lane < kb) lcol[lane] = dk != 0.0 ? F[lane + k * ld] / dk : 0.0;
+      __syncthreads();
+      if (dk != 0.0) {
+        const int i = lane;
+        if (i > k && i < kb) {
+          const double li = lcol[i];
+          for (int j = k + 1 + wave; j <= i; j += 4) F[i + j * ld] -= li * F[j + k * ld];
+        }
+      }
+      __syncthreads();
+      if (wave == 0 && lane > k && lane < kb) {
+        F[lane + k * ld] = lcol[lane];
+        maxl = fmax(maxl, fabs(lcol[lane]));
+      }
+      if (tid == 0) F[k + k * ld] = 1.0;
+      __syncthreads();
+      k += 1;
+    } else {
+      const double a = F[k + k * ld], b = F[(k + 1) + k * ld], c = F[(k + 1) + (k + 1) * ld];
+      const double det = a * c - b * b;
+      if (tid == 0) {
+        d[k] = a; e[k] = b; d[k + 1] = c; e[k + 1] = 0.0;
+        const double tr = a + c;
+        if (det < 0) { cnt.neg++; cnt.pos++; }
+        else if (det > 0) { if (tr < 0) cnt.neg += 2; else cnt.pos += 2; }
+        else { cnt.zero++; if (tr < 0) cnt.neg++; else if (tr > 0) cnt.pos++; else cnt.zero++; }
+        cnt.n2x2++;
+        const double m = 0.5 * tr, q = sqrt(0.25 * (a - c) * (a - c) + b * b);
+        cnt.mind = fmin(cnt.mind, fmin(fabs(m - q), fabs(m + q)));
+      }
+      double* lcol2 = lcol + kNB;
+      if (wave == 0 && lane > k + 1 && lane < kb) {
+        const double w1 = F[lane + k * ld], w2 = F[lane + (k + 1) * ld];
+        lcol[lane] = (c * w1 - b * w2) / det;
+        lcol2[lane] = (a * w2 - b * w1) / det;
+      }
+      __syncthreads();
+      {
+        const int i = lane;
+        if (i > k + 1 && i < kb) {
+          const double l1 = lcol[i], l2 = lcol2[i];
+          for (int j = k + 2 + wave; j <= i; j += 4)
+            F[i + j * ld] -= l1 * F[j + k * ld] + l2 * F[j + (k + 1) * ld];
+        }
+      }
+      __syncthreads();
+      if (wave == 0 && lane > k + 1 && lane < kb) {
+        F[lane + k * ld] = lcol[lane];
+        F[lane + (k + 1) * ld] = lcol2[lane];
+        maxl = fmax(maxl, fmax(fabs(lcol[lane]), fabs(lcol2[lane])));
+      }
+      if (tid == 0) { F[k + k * ld] = 1.0; F[(k + 1) + k * ld] = 0.0; F[(k + 1) + (k + 1) * ld] = 1.0; }
+      __syncthreads();
+      k += 2;
+    }
+  }
+  if (wave == 0) {
+    for (int off = 32; off > 0; off >>= 1) maxl = fmax(maxl, __shfl_xor(maxl, off));
+    if (lane == 0) cnt.maxl = fmax(cnt.maxl, maxl);
+  }
 }
 
 __device__ inline void flush_counts(const BKCounts& c, FactStats* st) {
@@ -353,12 +531,15 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* fronts, int t,
                                                     double* L, double* D, double* E,
                                                     int32_t* tperm, double* tinv, FactStats* st) {
-  __shared__ double T[kNB * kNB];
+  constexpr int LD = kNB + 1;   // padded: row walks across lanes hit distinct LDS banks
+  __shared__ double T[kNB * LD];
+  __shared__ double Linv[kNB * LD];
   __shared__ double sv[(NT + 63) / 64];
   __shared__ int si[(NT + 63) / 64];
   __shared__ int lp[kNB];
   __shared__ double dd[kNB], ee[kNB];
   __shared__ double lcol[2 * kNB];
+  __shared__ int dec[2];
   const int s = fronts[blockIdx.x];
   const int tid = threadIdx.x;
   const int64_t f0 = M.sfirst[s];
@@ -367,35 +548,71 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
   const int k0 = t * kNB;
   const int kb = min(kNB, ns - k0);
   double* Lp = L + M.lptr[s];
-  for (int x = tid; x < kb * kb; x += NT) {
-    const int i = x % kb, j = x / kb;
-    T[i + j * kb] = i >= j ? Lp[(k0 + i) + (int64_t)(k0 + j) * nf] : 0.0;
+  constexpr int U = 16;   // independent global accesses in flight per thread
+  for (int x0 = 0; x0 < kb * kb; x0 += NT * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = x0 + u * NT + tid;
+      const int i = x % kb, j = x / kb;
+      v[u] = (x < kb * kb && i >= j) ? Lp[(k0 + i) + (int64_t)(k0 + j) * nf] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = x0 + u * NT + tid;
+      if (x < kb * kb) T[(x % kb) + (x / kb) * LD] = v[u];
+    }
   }
   __syncthreads();
   BKCounts cnt{0, 0, 0, 0, INFINITY, 0.0};
-  bk_factor_lds<NT>(T, kb, kb, kb, lp, dd, ee, lcol, cnt, sv, si);
-  for (int x = tid; x < kb * kb; x += NT) {
-    const int i = x % kb, j = x / kb;
-    if (i >= j) Lp[(k0 + i) + (int64_t)(k0 + j) * nf] = T[i + j * kb];
+  bk_tile_lds(T, LD, kb, lp, dd, ee, lcol, cnt, dec);
+  __syncthreads();
+  for (int x0 = 0; x0 < kb * kb; x0 += NT * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = x0 + u * NT + tid;
+      v[u] = x < kb * kb ? T[(x % kb) + (x / kb) * LD] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = x0 + u * NT + tid;
+      const int i = x % kb, j = x / kb;
+      if (x < kb * kb && i >= j) Lp[(k0 + i) + (int64_t)(k0 + j) * nf] = v[u];
+    }
   }
   for (int q = tid; q < kb; q += NT) {
     D[f0 + k0 + q] = dd[q];
     E[f0 + k0 + q] = ee[q];
     tperm[f0 + k0 + q] = lp[q];
   }
-  // inverse of the unit-lower tile factor, column c by lane c (zero-padded to kNB)
-  double* Ti = tinv + M.tptr[s];
-  for (int c = tid; c < kNB; c += NT) {
-    for (int r = 0; r < kNB; r++) {
-      double x;
-      if (r < c || r >= kb || c >= kb) x = (r == c) ? 1.0 : 0.0;
-      else if (r == c) x = 1.0;
-      else {
-        x = 0.0;
-        for (int p = c; p < r; p++) x -= T[r + p * kb] * Ti[p + (int64_t)c * kNB];
-      }
-      Ti[r + (int64_t)c * kNB] = x;
+  // inverse of the unit-lower tile factor in LDS (zero-padded to kNB), axpy form:
+  // Linv = I; for p: Linv(r, c) -= L(r, p) Linv(p, c) for r > p >= c -- row p of
+  // Linv is final once step p starts; then one coalesced copy to the tile slot
+  for (int x = tid; x < kNB * kNB; x += NT) {
+    const int r = x % kNB, c = x / kNB;
+    Linv[r + c * LD] = r == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int p = 0; p + 1 < kb; p++) {
+    const int w = p + 1, cnt2 = (kb - 1 - p) * w;
+    for (int x = tid; x < cnt2; x += NT) {
+      const int r = p + 1 + x / w, c = x % w;
+      Linv[r + c * LD] -= T[r + p * LD] * Linv[p + c * LD];
     }
+    __syncthreads();
+  }
+  __syncthreads();
+  double* Ti = tinv + M.tptr[s];
+  for (int x0 = 0; x0 < kNB * kNB; x0 += NT * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = x0 + u * NT + tid;
+      v[u] = Linv[(x % kNB) + (x / kNB) * LD];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) Ti[x0 + u * NT + tid] = v[u];
   }
   if (tid == 0) flush_counts(cnt, st);
 }
@@ -437,12 +654,23 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
     ee[q] = q < kb ? E[f0 + k0 + q] : 0.0;
     pp[q] = q < kb ? tperm[f0 + k0 + q] : 0;
   }
-  for (int x = tid; x < kNB * kNB; x += NT) Bs[x] = Ti[x];
-  __syncthreads();
   const int nr = min(kTile, nf - r0);
-  for (int x = tid; x < kTile * kNB; x += NT) {
-    const int r = x % kTile, q = x / kTile;
-    As[x] = (r < nr && q < kb) ? Lp[(r0 + r) + (int64_t)(k0 + pp[q]) * nf] : 0.0;
+  __syncthreads();   // pp[] visible
+  {
+    constexpr int U = kTile * kNB / NT;   // 16 loads of each operand per thread, all in flight
+    double va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = u * NT + tid;
+      const int r = x % kTile, q = x / kTile;
+      vb[u] = Ti[x];
+      va[u] = (r < nr && q < kb) ? Lp[(r0 + r) + (int64_t)(k0 + pp[q]) * nf] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      As[u * NT + tid] = va[u];
+      Bs[u * NT + tid] = vb[u];
+    }
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
@@ -535,11 +763,22 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
   const double* Lp = f.Lp;
   const double* Wp = W + M.wptr[s];
   const int tid = threadIdx.x;
-  for (int x = tid; x < kTile * kNB; x += NT) {
-    const int r = x % kTile, q = x / kTile;
-    const bool qok = q < kb;
-    As[x] = (qok && ib + r < ie) ? Wp[(ib + r) + (int64_t)q * f.nf] : 0.0;
-    Bs[x] = (qok && jb + r < je) ? Lp[(jb + r) + (int64_t)(k0 + q) * f.nf] : 0.0;
+  {
+    constexpr int U = kTile * kNB / NT;   // 16 loads of each operand per thread, all in flight
+    double va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = u * NT + tid;
+      const int r = x % kTile, q = x / kTile;
+      const bool qok = q < kb;
+      va[u] = (qok && ib + r < ie) ? Wp[(ib + r) + (int64_t)q * f.nf] : 0.0;
+      vb[u] = (qok && jb + r < je) ? Lp[(jb + r) + (int64_t)(k0 + q) * f.nf] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      As[u * NT + tid] = va[u];
+      Bs[u * NT + tid] = vb[u];
+    }
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
@@ -629,7 +868,7 @@ void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count
                         double* L, double* D, double* E, int32_t* tperm, double* tinv,
                         FactStats* st, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_tile_factor<64>, dim3(count), dim3(64), 0, s, M, fronts, t, L, D, E, tperm,
+  hipLaunchKernelGGL(k_tile_factor<256>, dim3(count), dim3(256), 0, s, M, fronts, t, L, D, E, tperm,
                      tinv, st);
 }
 
