@@ -157,6 +157,15 @@ kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int
 kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double g,
                             double* grad_a, double* grad_b);
 
+/* Measurement: one FP64 factorization of A - sigma B with a HIP event pair around
+ * every kernel launch on the context stream.  out (nout >= 20 doubles) receives
+ *   [0] elapsed seconds (first to last event), [1] algorithmic flops of one
+ *   factorization (exact structure), [2] the same over the padded fronts,
+ *   [3 + 3c], [4 + 3c], [5 + 3c] for kernel class c = 0..4 (small fronts, large-front
+ *   assembly, pivot tiles, panel solves, Schur updates): seconds, dense operation
+ *   count of those launches, number of launches; [18] nu(sigma). */
+kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t nout);
+
 /* Diagnostics: one v_mfma_f64_16x16x4 on device 0, zero accumulator; lane l of
  * the wavefront supplies A[l] and B[l] (64 doubles each) and result register r
  * of lane l lands in D[4 l + r] (256 doubles).  Host pointers.  Used by the

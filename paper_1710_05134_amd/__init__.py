@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
                            C.POINTER(pd), C.POINTER(kth_info), C.POINTER(C.c_int)], C.c_int),
         "kth_eig_backward": ([vp, C.c_double, pd, C.c_double, pd, pd], C.c_int),
         "kth_debug_mfma_probe": ([pd, pd, pd], C.c_int),
+        "kth_profile_factor": ([vp, C.c_double, pd, C.c_int32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -200,6 +201,16 @@ class Pencil:
         _check(lib().kth_inertia_batch(self.h, s.size, _p(s, C.c_double), _p(out, C.c_int64)),
                self.ctx.h)
         return out
+
+    def profile_factor(self, sigma: float) -> dict:
+        """One factorization with per-kernel-class event timing (see kth.h)."""
+        out = np.zeros(20)
+        _check(lib().kth_profile_factor(self.h, float(sigma), _p(out, C.c_double), 20), self.ctx.h)
+        names = ("small", "assemble", "tile", "trsm", "schur")
+        d = dict(total_s=out[0], flops=out[1], flops_padded=out[2], nu=int(out[18]))
+        for c, nm in enumerate(names):
+            d[nm] = dict(seconds=out[3 + 3 * c], flops=out[4 + 3 * c], launches=int(out[5 + 3 * c]))
+        return d
 
     def factor(self, sigma: float, precision: int = KTH_FP64) -> "Factor":
         return Factor(self, sigma, precision)

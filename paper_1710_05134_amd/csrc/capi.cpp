@@ -307,6 +307,28 @@ kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double
   });
 }
 
+kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t nout) {
+  if (!p || !out || nout < 20) return KTH_EINVAL;
+  return guarded(&p->ctx->c, [&] {
+    set_device(p->ctx->c);
+    FactorProfile prof;
+    NumFactor& F = *p->p.scratch;
+    factor_enqueue(p->p, F, sigma, false, &prof);
+    factor_profile_finish(p->p, prof);
+    factor_read_stats(p->p, F);
+    for (int q = 0; q < nout; q++) out[q] = 0.0;
+    out[0] = prof.total;
+    out[1] = p->p.S.flops;
+    out[2] = p->p.S.flops_padded;
+    for (int c = 0; c < PROF_NCLASS; c++) {
+      out[3 + 3 * c] = prof.time[c];
+      out[4 + 3 * c] = prof.flops[c];
+      out[5 + 3 * c] = (double)prof.launches[c];
+    }
+    out[18] = (double)F.hs.neg;
+  });
+}
+
 kth_status kth_debug_mfma_probe(const double* A, const double* B, double* D) {
   return guarded(nullptr, [&] {
     double *dA, *dB, *dD;

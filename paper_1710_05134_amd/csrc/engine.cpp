@@ -153,6 +153,7 @@ static void build_schedule(Pencil& P) {
   }
   Ctx* c = P.ctx;
   P.d_sched.upload(c, sched);
+  P.h_sched = sched;
   P.d_wptr.upload(c, wptr);
   P.d_tptr.upload(c, tptr);
   P.d_tilew.upload(c, tilew);
@@ -250,9 +251,40 @@ void factor_alloc(Pencil& P, NumFactor& F) {
   F.stats.alloc(c, 1);
 }
 
-void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b) {
+FactorProfile::~FactorProfile() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+namespace {
+struct ProfScope {
+  FactorProfile* p;
+  hipStream_t st;
+  int cls;
+  ProfScope(FactorProfile* pr, hipStream_t s, int c, double flops) : p(pr), st(s), cls(c) {
+    if (!p) return;
+    hipEvent_t e;
+    KTH_HIP(hipEventCreate(&e));
+    KTH_HIP(hipEventRecord(e, st));
+    p->ev.push_back(e);
+    p->cls.push_back(c);
+    p->flops[c] += flops;
+    p->launches[c]++;
+  }
+  ~ProfScope() {
+    if (!p) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) == hipSuccess) {
+      (void)hipEventRecord(e, st);
+      p->ev.push_back(e);
+    }
+  }
+};
+}  // namespace
+
+void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b, FactorProfile* prof) {
   Ctx* c = P.ctx;
   hipStream_t st = c->stream;
+  const Symbolic& S = P.S;
   F.sigma = sigma;
   F.have_stats = false;
   const double sv = mode_b ? -1.0 : sigma;   // B = fma(-(-1), b, 0)
@@ -261,24 +293,71 @@ void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b) {
   launch_set_scalar(P.sig.get(), sv, st);
   launch_fill_stats(F.stats.get(), st);
   const int32_t* sched = P.d_sched.get();
+  const std::vector<int32_t>& hs = P.h_sched;
   for (const LevelPlan& lp : P.levels) {
-    launch_small_fronts(P.meta, sched + lp.small_off, lp.small_cnt, lp.small_maxnf, av, bv,
-                        P.sig.get(), F.L.get(), P.U.get(), F.D.get(), F.E.get(), F.tperm.get(),
-                        F.stats.get(), st);
+    if (lp.small_cnt > 0) {
+      double fl = 0;
+      if (prof)
+        for (int32_t q = 0; q < lp.small_cnt; q++) {
+          const int32_t s = hs[lp.small_off + q];
+          for (int64_t j = 0; j < S.ns(s); j++) { double cc = (double)(S.nf(s) - 1 - j); fl += cc * cc + 2 * cc; }
+        }
+      ProfScope ps(prof, st, PROF_SMALL, fl);
+      launch_small_fronts(P.meta, sched + lp.small_off, lp.small_cnt, lp.small_maxnf, av, bv,
+                          P.sig.get(), F.L.get(), P.U.get(), F.D.get(), F.E.get(), F.tperm.get(),
+                          F.stats.get(), st);
+    }
     if (lp.large_cnt == 0) continue;
-    launch_front_init(P.meta, reinterpret_cast<const Int2*>(sched + lp.init_off), lp.init_cnt, av,
-                      bv, P.sig.get(), F.L.get(), P.U.get(), st);
+    {
+      ProfScope ps(prof, st, PROF_INIT, 0.0);
+      launch_front_init(P.meta, reinterpret_cast<const Int2*>(sched + lp.init_off), lp.init_cnt, av,
+                        bv, P.sig.get(), F.L.get(), P.U.get(), st);
+    }
     for (const StepPlan& sp : lp.steps) {
-      launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, F.L.get(), F.D.get(),
-                         F.E.get(), F.tperm.get(), P.Tinv.get(), F.stats.get(), st);
-      launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm_off), sp.trsm_cnt, sp.t,
-                        F.L.get(), P.W.get(), F.D.get(), F.E.get(), F.tperm.get(), P.Tinv.get(),
-                        F.stats.get(), st);
-      launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles, sp.t,
-                   F.L.get(), P.U.get(), P.W.get(), st);
+      double fl_tile = 0, fl_trsm = 0, fl_schur = 0;
+      if (prof)
+        for (int32_t q = 0; q < sp.nfronts; q++) {
+          const int32_t s = hs[lp.large_off + q];
+          const double ns = (double)S.ns(s), nf = (double)S.nf(s);
+          const double k0 = (double)sp.t * kNB, kb = std::min<double>(kNB, ns - k0);
+          const double R = nf - k0 - kb;   // rows below the tile
+          for (int64_t j = 0; j < (int64_t)kb; j++) { double cc = kb - 1 - j; fl_tile += cc * cc + 2 * cc; }
+          fl_trsm += R * (kb * kb + kb);      // R rows: triangular solve + diagonal scaling
+          fl_schur += kb * R * (R + 1);       // rank-kb update of the R x R lower triangle
+        }
+      {
+        ProfScope ps(prof, st, PROF_TILE, fl_tile);
+        launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, F.L.get(), F.D.get(),
+                           F.E.get(), F.tperm.get(), P.Tinv.get(), F.stats.get(), st);
+      }
+      {
+        ProfScope ps(prof, st, PROF_TRSM, fl_trsm);
+        launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm_off), sp.trsm_cnt,
+                          sp.t, F.L.get(), P.W.get(), F.D.get(), F.E.get(), F.tperm.get(),
+                          P.Tinv.get(), F.stats.get(), st);
+      }
+      {
+        ProfScope ps(prof, st, PROF_SCHUR, fl_schur);
+        launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
+                     sp.t, F.L.get(), P.U.get(), P.W.get(), st);
+      }
     }
   }
   KTH_HIP(hipGetLastError());
+}
+
+void factor_profile_finish(Pencil& P, FactorProfile& prof) {
+  P.ctx->sync();
+  for (size_t q = 0; q + 1 < prof.ev.size(); q += 2) {
+    float ms = 0;
+    KTH_HIP(hipEventElapsedTime(&ms, prof.ev[q], prof.ev[q + 1]));
+    prof.time[prof.cls[q / 2]] += ms * 1e-3;
+  }
+  if (prof.ev.size() >= 2) {
+    float ms = 0;
+    KTH_HIP(hipEventElapsedTime(&ms, prof.ev.front(), prof.ev.back()));
+    prof.total = ms * 1e-3;
+  }
 }
 
 void factor_read_stats(Pencil& P, NumFactor& F) {

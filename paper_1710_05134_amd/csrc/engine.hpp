@@ -111,6 +111,7 @@ struct Pencil {
   DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched;
   FrontMeta meta{};
   std::vector<LevelPlan> levels;
+  std::vector<int32_t> h_sched;   // host copy of the schedule array
   SolvePlan splan;
   int64_t wsize = 0;   // workspace doubles
   int64_t tsize = 0;   // tile-inverse doubles
@@ -134,12 +135,27 @@ struct NumFactor {
   DBuf<double> xe, ye, R, partial;
 };
 
+// Per-kernel-class timing of one factorization (HIP events on the context stream).
+enum { PROF_SMALL = 0, PROF_INIT, PROF_TILE, PROF_TRSM, PROF_SCHUR, PROF_NCLASS };
+struct FactorProfile {
+  std::vector<hipEvent_t> ev;       // pairs (start, stop)
+  std::vector<int> cls;             // class of each pair
+  double time[PROF_NCLASS] = {0};   // seconds
+  double flops[PROF_NCLASS] = {0};  // dense-front operation counts of the launches
+  int64_t launches[PROF_NCLASS] = {0};
+  double total = 0;                 // seconds, first to last event
+  ~FactorProfile();
+};
+
 void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
                  const double* a, const double* b, uint32_t flags);
 void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_ptrs);
 void factor_alloc(Pencil& P, NumFactor& F);
 // Enqueue the numeric factorization of A - sigma B (mode_b: factor B itself).
-void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b);
+void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b,
+                    FactorProfile* prof = nullptr);
+// Resolve the events of a profiled factorization (synchronises the stream).
+void factor_profile_finish(Pencil& P, FactorProfile& prof);
 // Read back the inertia statistics (synchronises the stream).
 void factor_read_stats(Pencil& P, NumFactor& F);
 // x = (A - sigma B)^{-1} b, device vectors (enqueue only).
