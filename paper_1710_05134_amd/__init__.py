@@ -282,6 +282,23 @@ class Factor:
             pass
 
 
+def eig_batch(ctx: Context, pencils, ks, opts: kth_opts | None = None, want_x=True, **kw):
+    """kth_eig_batch: list of (status, lambda, x, info dict), one per pencil."""
+    o = default_opts(**kw) if opts is None else opts
+    npen = len(pencils)
+    hs = (C.c_void_p * npen)(*[p.h.value for p in pencils])
+    kk = np.ascontiguousarray(ks, dtype=np.int64)
+    lam = np.zeros(npen)
+    xs = [np.zeros(p.n) for p in pencils] if want_x else None
+    xptr = (C.POINTER(C.c_double) * npen)(*[_p(x, C.c_double) for x in xs]) if want_x else None
+    infos = (kth_info * npen)()
+    per = (C.c_int * npen)()
+    _check(lib().kth_eig_batch(ctx.h, npen, hs, _p(kk, C.c_int64), C.byref(o), _p(lam, C.c_double),
+                               xptr, infos, per), ctx.h)
+    return [(int(per[i]), float(lam[i]), xs[i] if want_x else None, infos[i].as_dict())
+            for i in range(npen)]
+
+
 def default_opts(**kw) -> kth_opts:
     o = kth_opts()
     lib().kth_opts_default(C.byref(o))
