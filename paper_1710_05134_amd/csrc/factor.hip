@@ -763,6 +763,30 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
   const double* Lp = f.Lp;
   const double* Wp = W + M.wptr[s];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  // wave's 32x32 sub-tile: rows (i) wr.., columns (j) wc..
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // C tile base: chunks never straddle ns, so the tile lies in the panel or in the update block
+  double* Cb;
+  int64_t ldc;
+  if (jb < f.ns) { Cb = f.Lp + ib + (int64_t)jb * f.nf; ldc = f.nf; }
+  else { Cb = f.Ub + (ib - f.ns) + (int64_t)(jb - f.ns) * f.nu; ldc = f.nu; }
+  // Output layout with A = L rows (j) and B = W rows (i): lane l holds i = l % 16 of
+  // its block and j = 4 r + l / 16 for register r -> 16 consecutive rows per column.
+  const int il = lane & 15, jl = lane >> 4;
+  const bool diag = (bi == bj);
+  // prefetch the C entries this thread will update (overlaps the operand staging)
+  double cv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int i = wr + a * 16 + il, j = wc + b * 16 + 4 * r + jl;
+        const bool ok = (ib + i < ie) && (jb + j < je) && (!diag || i >= j);
+        cv[a][b][r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
+      }
   {
     constexpr int U = kTile * kNB / NT;   // 16 loads of each operand per thread, all in flight
     double va[U], vb[U];
@@ -781,8 +805,6 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
     }
   }
   __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;  // wave's 32x32 sub-tile
   double4v acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; a++)
@@ -790,32 +812,29 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
     for (int b = 0; b < 2; b++) acc[a][b] = (double4v){0.0, 0.0, 0.0, 0.0};
   const int m = lane & 15, kk = lane >> 4;
   for (int q0 = 0; q0 < kNB; q0 += 4) {
-    double av[2], bv[2];
+    double wv[2], lv[2];
 #pragma unroll
-    for (int a = 0; a < 2; a++) av[a] = As[(wr + a * 16 + m) + (q0 + kk) * kTile];
+    for (int a = 0; a < 2; a++) wv[a] = As[(wr + a * 16 + m) + (q0 + kk) * kTile];
 #pragma unroll
-    for (int b = 0; b < 2; b++) bv[b] = Bs[(wc + b * 16 + m) + (q0 + kk) * kTile];
+    for (int b = 0; b < 2; b++) lv[b] = Bs[(wc + b * 16 + m) + (q0 + kk) * kTile];
+    // D(m = j, n = i) = sum_q L(j, q) W(i, q)
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
       for (int b = 0; b < 2; b++)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[b], wv[a], acc[a][b], 0, 0, 0);
   }
   // write back: C(i, j) -= acc for i >= j inside the chunk bounds
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++) {
-      const int j = jb + wc + b * 16 + (lane & 15);
+    for (int b = 0; b < 2; b++)
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int i = ib + wr + a * 16 + 4 * r + (lane >> 4);   // register r: row 4r + lane/16
-        if (i < ie && j < je && i >= j) {
-          double* p = f.at(i, j);
-          *p -= acc[a][b][r];
-        }
+        const int i = wr + a * 16 + il, j = wc + b * 16 + 4 * r + jl;
+        const bool ok = (ib + i < ie) && (jb + j < je) && (!diag || i >= j);
+        if (ok) Cb[i + (int64_t)j * ldc] = cv[a][b][r] - acc[a][b][r];
       }
-    }
 }
 
 __global__ void k_set_scalar(double* p, double v) {
