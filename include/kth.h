@@ -94,7 +94,10 @@ kth_status kth_pencil_destroy(kth_pencil p);
  * eigenvalues of D.  nzero (may be NULL) receives the number of exactly zero
  * pivots; if it is nonzero the call returns KTH_ESINGULAR (nu still written). */
 kth_status kth_inertia(kth_pencil p, double sigma, int64_t* nu, int64_t* nzero);
-/* nu at nsigma shifts in one batched call (multisection).  nu: nsigma entries. */
+/* nu at nsigma shifts (multisection): the factorizations advance together through
+ * the level schedule, as many at a time as free device memory allows (at most
+ * 64), batch index = grid dimension y.  nu: nsigma entries (always written);
+ * returns KTH_ESINGULAR if any shift gives an exactly zero pivot. */
 kth_status kth_inertia_batch(kth_pencil p, int32_t nsigma, const double* sigmas, int64_t* nu);
 
 /* Numeric factor of A - sigma B kept for solves (the linear systems of Alg. 2 and

@@ -208,11 +208,36 @@ void solve_many(Pencil& P, NumFactor& F, int32_t nrhs, const double* r, int64_t 
   c->sync();
 }
 
-void inertia_batch(Pencil& P, int32_t nsigma, const double* sigmas, int64_t* nu) {
-  for (int32_t i = 0; i < nsigma; i++) {
-    if (!std::isfinite(sigmas[i])) throw Error(KTH_EINVAL, "sigma must be finite");
-    nu[i] = count_nu(P, sigmas[i], nullptr, nullptr);
+// nu at many shifts: batches of factorizations advancing together through the
+// level schedule (one launch sequence per batch); returns the zero-pivot count.
+int64_t inertia_batch_counts(Pencil& P, int32_t nsigma, const double* sigmas, int64_t* nu,
+                             int64_t* nzero) {
+  if (nsigma <= 0) return 0;
+  const int cap = factor_batch_capacity(P, nsigma);
+  if (!P.batchF || P.batchF->nb < cap) {
+    P.batchF.reset(new NumFactor());
+    factor_alloc(P, *P.batchF, cap);
   }
+  NumFactor& F = *P.batchF;
+  int64_t zeros = 0;
+  for (int32_t i = 0; i < nsigma; i += F.nb) {
+    const int nb = std::min<int32_t>(F.nb, nsigma - i);
+    factor_enqueue_batch(P, F, sigmas + i, nb, false);
+    factor_read_stats(P, F, nb);
+    for (int q = 0; q < nb; q++) {
+      nu[i + q] = (int64_t)F.hsb[q].neg;
+      if (nzero) nzero[i + q] = (int64_t)F.hsb[q].zero;
+      zeros += (int64_t)F.hsb[q].zero;
+    }
+  }
+  return zeros;
+}
+
+void inertia_batch(Pencil& P, int32_t nsigma, const double* sigmas, int64_t* nu) {
+  for (int32_t i = 0; i < nsigma; i++)
+    if (!std::isfinite(sigmas[i])) throw Error(KTH_EINVAL, "sigma must be finite");
+  if (inertia_batch_counts(P, nsigma, sigmas, nu, nullptr) > 0)
+    throw Error(KTH_ESINGULAR, "a shift gives an exactly zero pivot");
 }
 
 kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, double* xout,
@@ -322,9 +347,19 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
         if (k <= nu) { su = sig; nu_ = nu; } else { sl = sig; nl = nu; }
       } else {
         std::vector<double> sg(ms);
-        std::vector<int64_t> cnt(ms);
+        std::vector<int64_t> cnt(ms), zc(ms);
         for (int i = 0; i < ms; i++) sg[i] = sl + (su - sl) * (double)(i + 1) / (double)(ms + 1);
-        for (int i = 0; i < ms; i++) cnt[i] = nu_checked(P, sg[i], 1e-3 * (su - sl) / (ms + 1), log, &nfac);
+        inertia_batch_counts(P, ms, sg.data(), cnt.data(), zc.data());
+        nfac += ms;
+        for (int i = 0; i < ms; i++) {
+          if (zc[i] != 0) {   // move that shift and count again on its own
+            nfac--;
+            cnt[i] = nu_checked(P, sg[i], 1e-3 * (su - sl) / (ms + 1), log, &nfac);
+          } else {
+            log.s.push_back(sg[i]);
+            log.nu.push_back(cnt[i]);
+          }
+        }
         s2++;
         double nsl = sl, nsu = su;
         int64_t nnl = nl, nnu = nu_;

@@ -214,10 +214,7 @@ void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const in
   P.meta.adst = P.d_adst.get();
   P.meta.tilew = P.d_tilew.get();
   P.meta.tptr = P.d_tptr.get();
-  P.U.alloc(ctx, (size_t)S.pool_size);
-  P.W.alloc(ctx, (size_t)P.wsize);
-  P.Tinv.alloc(ctx, (size_t)std::max<int64_t>(P.tsize, 1));
-  P.sig.alloc(ctx, 8);
+  P.ws_batches = 0;
   P.scratch.reset(new NumFactor());
   factor_alloc(P, *P.scratch);
   ctx->sync();
@@ -241,14 +238,38 @@ void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_
   }
 }
 
-void factor_alloc(Pencil& P, NumFactor& F) {
+static void ensure_workspace(Pencil& P, int nb) {
+  if (nb <= P.ws_batches) return;
   Ctx* c = P.ctx;
+  P.U.alloc(c, (size_t)P.S.pool_size * nb);
+  P.W.alloc(c, (size_t)P.wsize * nb);
+  P.Tinv.alloc(c, (size_t)std::max<int64_t>(P.tsize, 1) * nb);
+  P.ws_batches = nb;
+}
+
+void factor_alloc(Pencil& P, NumFactor& F, int nb) {
+  Ctx* c = P.ctx;
+  if (nb < 1 || nb > kMaxBatch) throw Error(KTH_EINVAL, "batch of factorizations out of range");
   F.p = &P;
-  F.L.alloc(c, (size_t)P.S.lptr[P.S.nsup]);
-  F.D.alloc(c, (size_t)P.n);
-  F.E.alloc(c, (size_t)P.n);
-  F.tperm.alloc(c, (size_t)P.n);
-  F.stats.alloc(c, 1);
+  F.nb = nb;
+  F.L.alloc(c, (size_t)P.S.lptr[P.S.nsup] * nb);
+  F.D.alloc(c, (size_t)P.n * nb);
+  F.E.alloc(c, (size_t)P.n * nb);
+  F.tperm.alloc(c, (size_t)P.n * nb);
+  F.stats.alloc(c, nb);
+  F.sig.alloc(c, nb);
+  ensure_workspace(P, nb);
+}
+
+int factor_batch_capacity(Pencil& P, int cap) {
+  size_t fr = 0, tot = 0;
+  KTH_HIP(hipMemGetInfo(&fr, &tot));
+  const double per = 8.0 * ((double)P.S.lptr[P.S.nsup] + (double)P.S.pool_size + (double)P.wsize +
+                            (double)P.tsize + 3.0 * (double)P.n);
+  // already-held workspace counts as available for the batch it serves
+  const double have = 8.0 * ((double)P.S.pool_size + (double)P.wsize + (double)P.tsize) * P.ws_batches;
+  int k = (int)((0.8 * (double)fr + have) / per);
+  return std::max(1, std::min(k, std::min(cap, kMaxBatch)));
 }
 
 FactorProfile::~FactorProfile() {
@@ -282,16 +303,31 @@ struct ProfScope {
 }  // namespace
 
 void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b, FactorProfile* prof) {
+  factor_enqueue_batch(P, F, &sigma, 1, mode_b, prof);
+}
+
+void factor_enqueue_batch(Pencil& P, NumFactor& F, const double* sigmas, int nb, bool mode_b,
+                          FactorProfile* prof) {
   Ctx* c = P.ctx;
   hipStream_t st = c->stream;
   const Symbolic& S = P.S;
-  F.sigma = sigma;
+  if (nb < 1 || nb > F.nb) throw Error(KTH_EINVAL, "batch larger than the factor storage");
+  ensure_workspace(P, nb);
+  F.sigma = sigmas[0];
   F.have_stats = false;
-  const double sv = mode_b ? -1.0 : sigma;   // B = fma(-(-1), b, 0)
+  double sv[kMaxBatch];
+  for (int i = 0; i < nb; i++) sv[i] = mode_b ? -1.0 : sigmas[i];   // B = fma(-(-1), b, 0)
   const double* av = mode_b ? P.zeros.get() : P.aval.get();
   const double* bv = P.bval.get();
-  launch_set_scalar(P.sig.get(), sv, st);
-  launch_fill_stats(F.stats.get(), st);
+  launch_set_scalars(F.sig.get(), nb, sv, st);
+  launch_fill_stats(F.stats.get(), nb, st);
+  Batch bt;
+  bt.sL = P.S.lptr[P.S.nsup];
+  bt.sU = P.S.pool_size;
+  bt.sW = P.wsize;
+  bt.sT = std::max<int64_t>(P.tsize, 1);
+  bt.sN = P.n;
+  bt.sig = F.sig.get();
   const int32_t* sched = P.d_sched.get();
   const std::vector<int32_t>& hs = P.h_sched;
   for (const LevelPlan& lp : P.levels) {
@@ -303,15 +339,15 @@ void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b, FactorPr
           for (int64_t j = 0; j < S.ns(s); j++) { double cc = (double)(S.nf(s) - 1 - j); fl += cc * cc + 2 * cc; }
         }
       ProfScope ps(prof, st, PROF_SMALL, fl);
-      launch_small_fronts(P.meta, sched + lp.small_off, lp.small_cnt, lp.small_maxnf, av, bv,
-                          P.sig.get(), F.L.get(), P.U.get(), F.D.get(), F.E.get(), F.tperm.get(),
+      launch_small_fronts(P.meta, sched + lp.small_off, lp.small_cnt, lp.small_maxnf, av, bv, bt,
+                          nb, F.L.get(), P.U.get(), F.D.get(), F.E.get(), F.tperm.get(),
                           F.stats.get(), st);
     }
     if (lp.large_cnt == 0) continue;
     {
       ProfScope ps(prof, st, PROF_INIT, 0.0);
       launch_front_init(P.meta, reinterpret_cast<const Int2*>(sched + lp.init_off), lp.init_cnt, av,
-                        bv, P.sig.get(), F.L.get(), P.U.get(), st);
+                        bv, bt, nb, F.L.get(), P.U.get(), st);
     }
     for (const StepPlan& sp : lp.steps) {
       double fl_tile = 0, fl_trsm = 0, fl_schur = 0;
@@ -327,19 +363,19 @@ void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b, FactorPr
         }
       {
         ProfScope ps(prof, st, PROF_TILE, fl_tile);
-        launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, F.L.get(), F.D.get(),
-                           F.E.get(), F.tperm.get(), P.Tinv.get(), F.stats.get(), st);
+        launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, bt, nb, F.L.get(),
+                           F.D.get(), F.E.get(), F.tperm.get(), P.Tinv.get(), F.stats.get(), st);
       }
       {
         ProfScope ps(prof, st, PROF_TRSM, fl_trsm);
         launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm_off), sp.trsm_cnt,
-                          sp.t, F.L.get(), P.W.get(), F.D.get(), F.E.get(), F.tperm.get(),
+                          sp.t, bt, nb, F.L.get(), P.W.get(), F.D.get(), F.E.get(), F.tperm.get(),
                           P.Tinv.get(), F.stats.get(), st);
       }
       {
         ProfScope ps(prof, st, PROF_SCHUR, fl_schur);
         launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
-                     sp.t, F.L.get(), P.U.get(), P.W.get(), st);
+                     sp.t, bt, nb, F.L.get(), P.U.get(), P.W.get(), st);
       }
     }
   }
@@ -360,14 +396,22 @@ void factor_profile_finish(Pencil& P, FactorProfile& prof) {
   }
 }
 
-void factor_read_stats(Pencil& P, NumFactor& F) {
-  KTH_HIP(hipMemcpyAsync(&F.hs, F.stats.get(), sizeof(FactStats), hipMemcpyDeviceToHost, P.ctx->stream));
+void factor_read_stats(Pencil& P, NumFactor& F, int nb) {
+  F.hsb.resize(nb);
+  KTH_HIP(hipMemcpyAsync(F.hsb.data(), F.stats.get(), sizeof(FactStats) * nb, hipMemcpyDeviceToHost,
+                         P.ctx->stream));
   P.ctx->sync();
+  F.hs = F.hsb[0];
   F.have_stats = true;
-  if ((int64_t)(F.hs.neg + F.hs.zero + F.hs.pos) != P.n)
-    throw Error(KTH_EDEVICE, "inertia counts do not add up to n (" + std::to_string(F.hs.neg) + "+" +
-                                 std::to_string(F.hs.zero) + "+" + std::to_string(F.hs.pos) + ")");
+  for (int i = 0; i < nb; i++) {
+    const FactStats& h = F.hsb[i];
+    if ((int64_t)(h.neg + h.zero + h.pos) != P.n)
+      throw Error(KTH_EDEVICE, "inertia counts do not add up to n (" + std::to_string(h.neg) + "+" +
+                                   std::to_string(h.zero) + "+" + std::to_string(h.pos) + ")");
+  }
 }
+
+void factor_read_stats(Pencil& P, NumFactor& F) { factor_read_stats(P, F, 1); }
 
 void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x) {
   Ctx* c = P.ctx;

@@ -113,23 +113,27 @@ struct Pencil {
   std::vector<LevelPlan> levels;
   std::vector<int32_t> h_sched;   // host copy of the schedule array
   SolvePlan splan;
-  int64_t wsize = 0;   // workspace doubles
-  int64_t tsize = 0;   // tile-inverse doubles
-  DBuf<double> U, W;   // update-block pool, panel workspace
-  DBuf<double> Tinv;   // inverses of the current pivot tiles
-  DBuf<double> sig;    // device scalars: [0] sigma of the running factorization
+  int64_t wsize = 0;   // workspace doubles per factorization
+  int64_t tsize = 0;   // tile-inverse doubles per factorization
+  int ws_batches = 0;  // factorizations the workspace below holds
+  DBuf<double> U, W;   // update-block pool, panel workspace (ws_batches copies)
+  DBuf<double> Tinv;   // inverses of the current pivot tiles (ws_batches copies)
   std::unique_ptr<NumFactor> scratch;   // factor reused by inertia-only calls
+  std::unique_ptr<NumFactor> batchF;    // batched inertia-only factorizations (multisection)
   double flops() const { return S.flops; }
 };
 
 struct NumFactor {
   Pencil* p = nullptr;
+  int nb = 1;                 // batched factorizations held (solves use batch 0)
   double sigma = 0;
   kth_precision prec = KTH_FP64;
   DBuf<double> L, D, E;
   DBuf<int32_t> tperm;
   DBuf<FactStats> stats;
-  FactStats hs{};
+  DBuf<double> sig;           // [nb] shifts on the device
+  FactStats hs{};             // batch 0
+  std::vector<FactStats> hsb; // all batches
   bool have_stats = false;
   // solve scratch
   DBuf<double> xe, ye, R, partial;
@@ -150,14 +154,20 @@ struct FactorProfile {
 void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
                  const double* a, const double* b, uint32_t flags);
 void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_ptrs);
-void factor_alloc(Pencil& P, NumFactor& F);
+void factor_alloc(Pencil& P, NumFactor& F, int nb = 1);
+// Largest batch of factorizations that fits in free device memory (<= cap).
+int factor_batch_capacity(Pencil& P, int cap);
 // Enqueue the numeric factorization of A - sigma B (mode_b: factor B itself).
 void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b,
                     FactorProfile* prof = nullptr);
+// Enqueue nb factorizations A - sigma_i B (i < nb <= F.nb) in one launch sequence.
+void factor_enqueue_batch(Pencil& P, NumFactor& F, const double* sigmas, int nb, bool mode_b,
+                          FactorProfile* prof = nullptr);
 // Resolve the events of a profiled factorization (synchronises the stream).
 void factor_profile_finish(Pencil& P, FactorProfile& prof);
-// Read back the inertia statistics (synchronises the stream).
+// Read back the inertia statistics of batch 0 / of nb batches (synchronises the stream).
 void factor_read_stats(Pencil& P, NumFactor& F);
+void factor_read_stats(Pencil& P, NumFactor& F, int nb);
 // x = (A - sigma B)^{-1} b, device vectors (enqueue only).
 void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x);
 

@@ -388,6 +388,7 @@ __device__ inline void flush_counts(const BKCounts& c, FactStats* st) {
 }
 
 __global__ void k_fill_stats(FactStats* st) {
+  st += blockIdx.x;
   if (threadIdx.x == 0) {
     st->neg = st->zero = st->pos = st->n2x2 = 0;
     st->min_d_bits = dbits(INFINITY);
@@ -402,9 +403,13 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_small_fronts(FrontMeta M, const int32_t* fronts,
                                                      const double* __restrict__ aval,
                                                      const double* __restrict__ bval,
-                                                     const double* sigma_dev, double* L, double* U,
+                                                     Batch bt, double* L, double* U,
                                                      double* D, double* E, int32_t* tperm,
                                                      FactStats* st) {
+  const int64_t bidx = blockIdx.y;
+  L += bidx * bt.sL; U += bidx * bt.sU; D += bidx * bt.sN; E += bidx * bt.sN;
+  tperm += bidx * bt.sN; st += bidx;
+  const double* sigma_dev = bt.sig + bidx;
   extern __shared__ double smem[];
   __shared__ double sv[NT / 64];
   __shared__ int si[NT / 64];
@@ -483,7 +488,10 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* tasks,
                                                    const double* __restrict__ aval,
                                                    const double* __restrict__ bval,
-                                                   const double* sigma_dev, double* L, double* U) {
+                                                   Batch bt, double* L, double* U) {
+  const int64_t bidx = blockIdx.y;
+  L += bidx * bt.sL; U += bidx * bt.sU;
+  const double* sigma_dev = bt.sig + bidx;
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, c0 = tk.b;
   const FrontRef f = front_ref(M, s, L, U);
@@ -529,8 +537,13 @@ __global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* task
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* fronts, int t,
-                                                    double* L, double* D, double* E,
+                                                    Batch bt, double* L, double* D, double* E,
                                                     int32_t* tperm, double* tinv, FactStats* st) {
+  {
+    const int64_t bidx = blockIdx.y;
+    L += bidx * bt.sL; D += bidx * bt.sN; E += bidx * bt.sN; tperm += bidx * bt.sN;
+    tinv += bidx * bt.sT; st += bidx;
+  }
   constexpr int LD = kNB + 1;   // padded: row walks across lanes hit distinct LDS banks
   __shared__ double T[kNB * LD];
   __shared__ double Linv[kNB * LD];
@@ -627,12 +640,17 @@ typedef double double4v __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* tasks, int t,
-                                                   double* L, double* W,
+                                                   Batch bt, double* L, double* W,
                                                    const double* __restrict__ D,
                                                    const double* __restrict__ E,
                                                    const int32_t* __restrict__ tperm,
                                                    const double* __restrict__ tinv,
                                                    FactStats* st) {
+  {
+    const int64_t bidx = blockIdx.y;
+    L += bidx * bt.sL; W += bidx * bt.sW; D += bidx * bt.sN; E += bidx * bt.sN;
+    tperm += bidx * bt.sN; tinv += bidx * bt.sT; st += bidx;
+  }
   __shared__ double As[kTile * kNB];   // S' rows x k, ld kTile; reused for W
   __shared__ double Bs[kNB * kNB];     // Linv(q, p) at q + p*kNB
   __shared__ double dd[kNB], ee[kNB];
@@ -738,7 +756,11 @@ __device__ inline void chunk_range(int c, int r0, int ns, int nf, int nc1, int& 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts,
                                               const int32_t* tile_prefix, int nfronts, int t,
-                                              double* L, double* U, const double* W) {
+                                              Batch bt, double* L, double* U, const double* W) {
+  {
+    const int64_t bidx = blockIdx.y;
+    L += bidx * bt.sL; U += bidx * bt.sU; W += bidx * bt.sW;
+  }
   __shared__ double As[kTile * kNB];  // W rows (i) x k, ld kTile
   __shared__ double Bs[kTile * kNB];  // L rows (j) x k, ld kTile
   // locate the front of this tile
@@ -841,6 +863,10 @@ __global__ void k_set_scalar(double* p, double v) {
   if (threadIdx.x == 0) *p = v;
 }
 
+__global__ void k_set_scalars(double* p, int n, SigmaPack pk) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = pk.v[threadIdx.x];
+}
+
 // Raw probe: lane l feeds a[l] and b[l]; c[4 l + r] receives result register r.
 __global__ void k_mfma_probe(const double* A, const double* B, double* Dout) {
   const int lane = threadIdx.x;
@@ -854,12 +880,12 @@ __global__ void k_mfma_probe(const double* A, const double* B, double* Dout) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-void launch_fill_stats(FactStats* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_stats, dim3(1), dim3(64), 0, s, st);
+void launch_fill_stats(FactStats* st, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_stats, dim3(nb), dim3(64), 0, s, st);
 }
 
 void launch_small_fronts(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t max_nf,
-                         const double* aval, const double* bval, const double* sigma_dev,
+                         const double* aval, const double* bval, const Batch& bt, int nb,
                          double* L, double* U, double* D, double* E, int32_t* tperm,
                          FactStats* st, hipStream_t s) {
   if (count <= 0) return;
@@ -871,44 +897,52 @@ void launch_small_fronts(const FrontMeta& M, const int32_t* fronts, int32_t coun
                               kSmallMaxNf * kSmallMaxNf * (int)sizeof(double));
     attr = true;
   }
-  hipLaunchKernelGGL(k_small_fronts<256>, dim3(count), dim3(256), lds, s, M, fronts, aval, bval,
-                     sigma_dev, L, U, D, E, tperm, st);
+  hipLaunchKernelGGL(k_small_fronts<256>, dim3(count, nb), dim3(256), lds, s, M, fronts, aval, bval,
+                     bt, L, U, D, E, tperm, st);
 }
 
 void launch_front_init(const FrontMeta& M, const Int2* tasks, int32_t count, const double* aval,
-                       const double* bval, const double* sigma_dev, double* L, double* U,
+                       const double* bval, const Batch& bt, int nb, double* L, double* U,
                        hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_front_init<256>, dim3(count), dim3(256), 0, s, M, tasks, aval, bval,
-                     sigma_dev, L, U);
+  hipLaunchKernelGGL(k_front_init<256>, dim3(count, nb), dim3(256), 0, s, M, tasks, aval, bval, bt,
+                     L, U);
 }
 
 void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t t,
-                        double* L, double* D, double* E, int32_t* tperm, double* tinv,
-                        FactStats* st, hipStream_t s) {
+                        const Batch& bt, int nb, double* L, double* D, double* E, int32_t* tperm,
+                        double* tinv, FactStats* st, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_tile_factor<256>, dim3(count), dim3(256), 0, s, M, fronts, t, L, D, E, tperm,
-                     tinv, st);
+  hipLaunchKernelGGL(k_tile_factor<256>, dim3(count, nb), dim3(256), 0, s, M, fronts, t, bt, L, D,
+                     E, tperm, tinv, st);
 }
 
-void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, double* L,
-                       double* W, const double* D, const double* E, const int32_t* tperm,
-                       const double* tinv, FactStats* st, hipStream_t s) {
+void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t,
+                       const Batch& bt, int nb, double* L, double* W, const double* D,
+                       const double* E, const int32_t* tperm, const double* tinv, FactStats* st,
+                       hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_panel_trsm<256>, dim3(count), dim3(256), 0, s, M, tasks, t, L, W, D, E,
-                     tperm, tinv, st);
+  hipLaunchKernelGGL(k_panel_trsm<256>, dim3(count, nb), dim3(256), 0, s, M, tasks, t, bt, L, W, D,
+                     E, tperm, tinv, st);
 }
 
 void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
-                  int32_t nfronts, int32_t ntiles, int32_t t, double* L, double* U, const double* W,
-                  hipStream_t s) {
+                  int32_t nfronts, int32_t ntiles, int32_t t, const Batch& bt, int nb, double* L,
+                  double* U, const double* W, hipStream_t s) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_schur<256>, dim3(ntiles), dim3(256), 0, s, M, fronts, tile_prefix, nfronts,
-                     t, L, U, W);
+  hipLaunchKernelGGL(k_schur<256>, dim3(ntiles, nb), dim3(256), 0, s, M, fronts, tile_prefix,
+                     nfronts, t, bt, L, U, W);
 }
 
 void launch_set_scalar(double* p, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, p, v);
+}
+
+void launch_set_scalars(double* p, int n, const double* v8, hipStream_t s) {
+  // up to kMaxBatch values passed by value (no host-memory lifetime issues, graph-safe)
+  SigmaPack pk;
+  for (int i = 0; i < n && i < kMaxBatch; i++) pk.v[i] = v8[i];
+  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, p, n, pk);
 }
 
 void launch_mfma_probe(const double* A, const double* B, double* D, hipStream_t s) {
