@@ -55,6 +55,8 @@ typedef void (*kth_free_fn)(void* ptr, void* user);
 /* pencil flags */
 #define KTH_DEVICE_PTRS    1u  /* value arrays of kth_pencil_set_values are device pointers */
 #define KTH_CHECK_SYMMETRY 2u  /* verify structural symmetry of the pattern (O(nnz log)) */
+/* solve flags (with KTH_DEVICE_PTRS) */
+#define KTH_SOLVE_UNREFINED 4u /* FP32 factor: one solve pass in the factor's precision, no refinement */
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run on,
  * or NULL for a stream owned by the context.  alloc/free: device allocator (both
@@ -62,6 +64,8 @@ typedef void (*kth_free_fn)(void* ptr, void* user);
  * Fails with KTH_EDEVICE if the device is not a gfx950 GPU. */
 kth_status kth_ctx_create(int device, void* hip_stream, kth_alloc_fn alloc, kth_free_fn free_fn,
                           void* user, kth_ctx* out);
+/* Releases the caller's handle.  Pencils hold their context and kept factors their
+ * pencil: a destroyed parent is freed when its last child is destroyed. */
 kth_status kth_ctx_destroy(kth_ctx ctx);
 const char* kth_status_string(kth_status s);
 const char* kth_last_error(kth_ctx ctx);   /* message of the last failing call on ctx ("" if none) */
@@ -101,13 +105,22 @@ kth_status kth_inertia(kth_pencil p, double sigma, int64_t* nu, int64_t* nzero);
 kth_status kth_inertia_batch(kth_pencil p, int32_t nsigma, const double* sigmas, int64_t* nu);
 
 /* Numeric factor of A - sigma B kept for solves (the linear systems of Alg. 2 and
- * Alg. 3).  KTH_FP32_IR factors in FP32 and refines each solve in FP64. */
+ * Alg. 3).  KTH_FP32_IR: the same factorization in FP32 storage and arithmetic
+ * (entries fma(-sigma, b, a) formed in FP64, then rounded; pivots and 2x2 blocks
+ * kept in FP64).  Every kth_solve on such a factor refines in FP64: with
+ * M = A - sigma B and residual r = R - M X formed in FP64, corrections from GMRES
+ * on M32^{-1} M (the FP32 factor as preconditioner, <= 20 steps each) are added
+ * until ||r||_inf <= 4 eps64 (||M||_inf ||x||_inf + ||R||_inf), where ||M||_inf is
+ * bounded by ||A||_inf + |sigma| ||B||_inf.  The solve returns KTH_ENOCONV (x: last
+ * iterate) if ||r||_inf fails to halve on two consecutive corrections or 4
+ * corrections do not reach the target. */
 kth_status kth_factor(kth_pencil p, double sigma, kth_precision prec, kth_factor_t* out);
 /* Inertia of a kept FP64 factor: counts of negative, zero and positive
  * eigenvalues of D (neg + zero + pos = n).  KTH_ESTATE for an FP32 factor. */
 kth_status kth_factor_inertia(kth_factor_t f, int64_t* neg, int64_t* zero, int64_t* pos);
 /* Solve (A - sigma B) X = R for nrhs columns (column-major, leading dims >= n).
- * r and x: host pointers, or device pointers with flags & KTH_DEVICE_PTRS. */
+ * r and x: host pointers, or device pointers with flags & KTH_DEVICE_PTRS.
+ * flags & KTH_SOLVE_UNREFINED: an FP32 factor is applied once, unrefined. */
 kth_status kth_solve(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr, double* x,
                      int64_t ldx, uint32_t flags);
 kth_status kth_factor_destroy(kth_factor_t f);
@@ -124,6 +137,7 @@ typedef struct {
   const double* start_vectors; /* optional host array [4][n]: row 0 stage 1, row 1 stage 3, rows 2.. restarts */
   const double* warm_interval; /* optional [2]: sigma_l, sigma_u (skip stages 1-2)             */
   const int64_t* warm_counts;  /* optional [2]: nu_l, nu_u matching warm_interval              */
+  double ir_tol;          /* FP32 shift-and-invert solves: target backward error (0: 4 eps64) */
 } kth_opts;
 
 typedef struct {
@@ -142,6 +156,10 @@ typedef struct {
   int32_t n_sigmas;           /* shifts whose inertia was computed (stage 1 and 2)            */
   double sigmas[128];         /* those shifts, in order (first 128)                            */
   int64_t nus[128];           /* their counts                                                  */
+  int32_t si_precision;       /* precision of the shift-and-invert factor in the end (kth_precision) */
+  int32_t ir_steps;           /* FP32-factor applications spent on refinement (all SI solves)  */
+  int32_t ir_fallback;        /* 1 if a stalled refinement switched the factor to FP64          */
+  double ir_max_berr;         /* largest backward error at exit of a refined solve             */
 } kth_info;
 
 void kth_opts_default(kth_opts* o);
@@ -174,6 +192,8 @@ kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t n
  * of lane l lands in D[4 l + r] (256 doubles).  Host pointers.  Used by the
  * tests to pin the operand layout the kernels assume. */
 kth_status kth_debug_mfma_probe(const double* A, const double* B, double* D);
+/* The same for one v_mfma_f32_16x16x4_f32 (float arrays of 64, 64 and 256). */
+kth_status kth_debug_mfma_probe_f32(const float* A, const float* B, float* D);
 
 #ifdef __cplusplus
 }

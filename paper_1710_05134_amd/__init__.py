@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libkth.so")
 KTH_OK, KTH_EINVAL, KTH_ENOMEM, KTH_EDEVICE, KTH_ENOTPD, KTH_ESINGULAR, KTH_ENOCONV, \
     KTH_ECLUSTER, KTH_ESTATE = range(9)
 KTH_FP64, KTH_FP32_IR = 0, 1
-KTH_DEVICE_PTRS, KTH_CHECK_SYMMETRY = 1, 2
+KTH_DEVICE_PTRS, KTH_CHECK_SYMMETRY, KTH_SOLVE_UNREFINED = 1, 2, 4
 ANALYZE_FIELDS = ("n", "nnz", "n_supervariables", "n_supernodes_fundamental", "n_supernodes",
                   "max_front", "max_pivot_block", "levels", "flops", "flops_padded", "nnz_l",
                   "nnz_l_padded", "front_pool_bytes", "factor_bytes", "t_order_s", "t_symbolic_s")
@@ -37,7 +37,7 @@ class kth_opts(C.Structure):
     _fields_ = [("m_max", C.c_int64), ("tau_res", C.c_double), ("tau_diff", C.c_double),
                 ("tau_len", C.c_double), ("max_lanczos", C.c_int32), ("multisection", C.c_int32),
                 ("seed", C.c_uint64), ("si_precision", C.c_int), ("start_vectors", C.c_void_p),
-                ("warm_interval", C.c_void_p), ("warm_counts", C.c_void_p)]
+                ("warm_interval", C.c_void_p), ("warm_counts", C.c_void_p), ("ir_tol", C.c_double)]
 
 
 class kth_info(C.Structure):
@@ -50,7 +50,9 @@ class kth_info(C.Structure):
                 ("min_pivot_rel", C.c_double), ("n_factorizations", C.c_int64),
                 ("flops_factor", C.c_double), ("t_task", C.c_double * 7),
                 ("peak_device_bytes", C.c_double), ("n_sigmas", C.c_int32),
-                ("sigmas", C.c_double * 128), ("nus", C.c_int64 * 128)]
+                ("sigmas", C.c_double * 128), ("nus", C.c_int64 * 128),
+                ("si_precision", C.c_int32), ("ir_steps", C.c_int32), ("ir_fallback", C.c_int32),
+                ("ir_max_berr", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -98,6 +100,7 @@ def lib() -> C.CDLL:
         "kth_eig_backward": ([vp, C.c_double, pd, C.c_double, pd, pd], C.c_int),
         "kth_debug_mfma_probe": ([pd, pd, pd], C.c_int),
         "kth_profile_factor": ([vp, C.c_double, pd, C.c_int32], C.c_int),
+        "kth_debug_mfma_probe_f32": ([C.POINTER(C.c_float)] * 3, C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -261,13 +264,15 @@ class Factor:
                self.pencil.ctx.h)
         return a.value, b.value, c.value
 
-    def solve(self, r):
+    def solve(self, r, refine: bool = True):
+        """X = (A - sigma B)^{-1} R; refine=False applies an FP32 factor once."""
         r = np.asfortranarray(r, dtype=np.float64)
         one = r.ndim == 1
         R = r.reshape(self.pencil.n, -1, order="F")
         X = np.zeros_like(R, order="F")
         _check(lib().kth_solve(self.h, R.shape[1], R.ctypes.data, self.pencil.n, X.ctypes.data,
-                               self.pencil.n, 0), self.pencil.ctx.h)
+                               self.pencil.n, 0 if refine else KTH_SOLVE_UNREFINED),
+               self.pencil.ctx.h)
         return X[:, 0] if one else X
 
     def close(self):
@@ -320,6 +325,14 @@ def default_opts(**kw) -> kth_opts:
             setattr(o, k, v)
     del keep
     return o
+
+
+def kth_debug_mfma_probe_f32(A, B):
+    A = np.ascontiguousarray(A, dtype=np.float32).reshape(-1)
+    B = np.ascontiguousarray(B, dtype=np.float32).reshape(-1)
+    D = np.zeros(256, dtype=np.float32)
+    _check(lib().kth_debug_mfma_probe_f32(_p(A, C.c_float), _p(B, C.c_float), _p(D, C.c_float)))
+    return D
 
 
 def kth_debug_mfma_probe(A, B):

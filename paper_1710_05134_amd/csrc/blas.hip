@@ -166,6 +166,55 @@ __global__ void k_residual(int64_t n, double lam, const double* __restrict__ ya,
     r[i] = ya[i] - lam * yb[i];
 }
 
+// r = rhs - (A - sigma B) x (rhs null: r = (A - sigma B) x), every entry formed as
+// fma(-sigma, b, a) (8 lanes per row)
+__global__ __launch_bounds__(NT) void k_shifted_residual(int64_t n, const int64_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ a,
+                                                         const double* __restrict__ b, double sigma,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ rhs, double* r) {
+  const int64_t row = (blockIdx.x * (int64_t)NT + threadIdx.x) >> 3;
+  const int sub = threadIdx.x & 7;
+  double s = 0.0;
+  if (row < n) {
+    const int64_t e = rowptr[row + 1];
+    for (int64_t q = rowptr[row] + sub; q < e; q += 8) s = fma(fma(-sigma, b[q], a[q]), x[col[q]], s);
+  }
+  for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 8);
+  if (row < n && sub == 0) r[row] = rhs ? rhs[row] - s : s;
+}
+
+// partial[blk] = max |x_i| over the block's rows; then out = max over blocks (fixed order)
+__global__ __launch_bounds__(NT) void k_absmax_partial(int64_t n, const double* __restrict__ x,
+                                                       double* partial) {
+  __shared__ double red[NT / 64];
+  const int64_t r0 = (int64_t)blockIdx.x * kDotRows;
+  const int64_t r1 = r0 + kDotRows < n ? r0 + kDotRows : n;
+  double m = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) m = fmax(m, fabs(x[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < NT / 64; q++) t = fmax(t, red[q]);
+    partial[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_max_partials(int nblk, const double* __restrict__ partial, double* out) {
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int q = 0; q < nblk; q++) t = fmax(t, partial[q]);
+  *out = t;
+}
+
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* y) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    y[i] = fma(a, x[i], y[i]);
+}
+
 // Hellmann-Feynman: per stored entry q of row r: ga = g x_r x_c, gb = -g lam x_r x_c
 __global__ __launch_bounds__(NT) void k_hf(int64_t n, const int64_t* __restrict__ rowptr,
                                            const int32_t* __restrict__ col, const double* __restrict__ x,
@@ -369,6 +418,23 @@ void scale_by_dev(int64_t n, const double* sdev, int idx, bool inv, double* y, h
 
 void residual(int64_t n, double lam, const double* ya, const double* yb, double* r, hipStream_t s) {
   hipLaunchKernelGGL(k_residual, dim3(blocks_for(n, NT * 4)), dim3(NT), 0, s, n, lam, ya, yb, r);
+}
+
+void shifted_residual(int64_t n, const int64_t* rowptr, const int32_t* col, const double* a,
+                      const double* b, double sigma, const double* x, const double* rhs, double* r,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_shifted_residual, dim3(blocks_for(n * 8, NT)), dim3(NT), 0, s, n, rowptr, col,
+                     a, b, sigma, x, rhs, r);
+}
+
+void absmax(int64_t n, const double* x, double* partial, double* out, hipStream_t s) {
+  const int nb = multidot_blocks(n);
+  hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(NT), 0, s, n, x, partial);
+  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(64), 0, s, nb, partial, out);
+}
+
+void axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n, NT * 4)), dim3(NT), 0, s, n, a, x, y);
 }
 
 void hf_gradient(int64_t n, const int64_t* rowptr, const int32_t* col, const double* x, double g,

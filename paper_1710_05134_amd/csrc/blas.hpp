@@ -30,6 +30,14 @@ void ritz_vectors(int64_t n, int j, int m, const double* V, int64_t ldv, const d
 void scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
 void scale_by_dev(int64_t n, const double* sdev, int idx, bool inv, double* y, hipStream_t s);
 void residual(int64_t n, double lam, const double* ya, const double* yb, double* r, hipStream_t s);
+// r = rhs - (A - sigma B) x (rhs null: r = (A - sigma B) x), entries fma(-sigma, b, a)
+// as in the factorization
+void shifted_residual(int64_t n, const int64_t* rowptr, const int32_t* col, const double* a,
+                      const double* b, double sigma, const double* x, const double* rhs, double* r,
+                      hipStream_t s);
+// *out = max_i |x_i| (partial: multidot_blocks(n) doubles)
+void absmax(int64_t n, const double* x, double* partial, double* out, hipStream_t s);
+void axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);
 void hf_gradient(int64_t n, const int64_t* rowptr, const int32_t* col, const double* x, double g,
                  double lam, double* ga, double* gb, hipStream_t s);
 // eigenvalues (ascending) and eigenvectors (columns of Y, j x j) of the

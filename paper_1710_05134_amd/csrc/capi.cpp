@@ -13,12 +13,17 @@
 
 using namespace kth;
 
+// Handles are reference counted: a pencil holds its context, a factor its pencil,
+// so the device memory of a child is released through a live parent whatever the
+// order in which the caller destroys them.
 struct kth_ctx_s {
   Ctx c;
+  int refs = 1;
 };
 struct kth_pencil_s {
   kth_ctx_s* ctx;
   Pencil p;
+  int refs = 1;
 };
 struct kth_factor_s {
   kth_pencil_s* pen;
@@ -48,6 +53,33 @@ kth_status guarded(Ctx* c, F&& fn) {
 }
 
 void set_device(Ctx& c) { KTH_HIP(hipSetDevice(c.device)); }
+
+void check_opts(const kth_opts& o) {
+  if (o.m_max < 1) throw Error(KTH_EINVAL, "m_max must be >= 1");
+  if (!(o.tau_res > 0) || !(o.tau_diff > 0)) throw Error(KTH_EINVAL, "tolerances must be > 0");
+  if (!(o.tau_len >= 0)) throw Error(KTH_EINVAL, "tau_len must be >= 0");
+  if (o.max_lanczos < 1) throw Error(KTH_EINVAL, "max_lanczos must be >= 1");
+  if (o.multisection < 1 || o.multisection > kMaxBatch)
+    throw Error(KTH_EINVAL, "multisection must be in [1, 64]");
+  if (o.si_precision != KTH_FP64 && o.si_precision != KTH_FP32_IR)
+    throw Error(KTH_EINVAL, "unknown si_precision");
+  if (!(o.ir_tol >= 0) || !std::isfinite(o.ir_tol)) throw Error(KTH_EINVAL, "ir_tol must be >= 0");
+}
+
+void ctx_release(kth_ctx_s* c) {
+  if (--c->refs > 0) return;
+  if (c->c.own_stream) (void)hipStreamDestroy(c->c.stream);
+  delete c;
+}
+
+void pencil_release(kth_pencil_s* p) {
+  if (--p->refs > 0) return;
+  kth_ctx_s* c = p->ctx;
+  (void)hipSetDevice(c->c.device);
+  (void)hipStreamSynchronize(c->c.stream);
+  delete p;
+  ctx_release(c);
+}
 
 }  // namespace
 
@@ -105,8 +137,7 @@ kth_status kth_ctx_create(int device, void* hip_stream, kth_alloc_fn alloc, kth_
 
 kth_status kth_ctx_destroy(kth_ctx ctx) {
   if (!ctx) return KTH_EINVAL;
-  if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
-  delete ctx;
+  ctx_release(ctx);
   return KTH_OK;
 }
 
@@ -156,7 +187,10 @@ kth_status kth_pencil_create(kth_ctx ctx, int64_t n, const int64_t* rowptr, cons
     set_device(ctx->c);
     pencil_init(p->p, &ctx->c, n, rowptr, col, a_val, b_val, flags);
   });
-  if (st == KTH_OK) *out = p.release();
+  if (st == KTH_OK) {
+    ctx->refs++;
+    *out = p.release();
+  }
   return st;
 }
 
@@ -173,9 +207,7 @@ kth_status kth_pencil_set_values(kth_pencil p, const double* a_val, const double
 
 kth_status kth_pencil_destroy(kth_pencil p) {
   if (!p) return KTH_EINVAL;
-  (void)hipSetDevice(p->ctx->c.device);
-  (void)hipStreamSynchronize(p->ctx->c.stream);
-  delete p;
+  pencil_release(p);
   return KTH_OK;
 }
 
@@ -216,7 +248,10 @@ kth_status kth_factor(kth_pencil p, double sigma, kth_precision prec, kth_factor
     set_device(p->ctx->c);
     numeric_factor(p->p, f->f, sigma, prec);
   });
-  if (st == KTH_OK) *out = f.release();
+  if (st == KTH_OK) {
+    p->refs++;
+    *out = f.release();
+  }
   return st;
 }
 
@@ -239,15 +274,18 @@ kth_status kth_solve(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr,
   return guarded(&p->ctx->c, [&] {
     if (ldr < p->p.n || ldx < p->p.n) throw Error(KTH_EINVAL, "leading dimension smaller than n");
     set_device(p->ctx->c);
-    solve_many(p->p, f->f, nrhs, r, ldr, x, ldx, (flags & KTH_DEVICE_PTRS) != 0);
+    solve_many(p->p, f->f, nrhs, r, ldr, x, ldx, (flags & KTH_DEVICE_PTRS) != 0,
+               (flags & KTH_SOLVE_UNREFINED) != 0);
   });
 }
 
 kth_status kth_factor_destroy(kth_factor_t f) {
   if (!f) return KTH_EINVAL;
-  (void)hipSetDevice(f->pen->ctx->c.device);
-  (void)hipStreamSynchronize(f->pen->ctx->c.stream);
+  kth_pencil_s* p = f->pen;
+  (void)hipSetDevice(p->ctx->c.device);
+  (void)hipStreamSynchronize(p->ctx->c.stream);
   delete f;
+  pencil_release(p);
   return KTH_OK;
 }
 
@@ -275,6 +313,7 @@ kth_status kth_eig(kth_pencil p, int64_t k, const kth_opts* opts, double* lambda
   kth_status st = KTH_OK;
   kth_status g = guarded(&p->ctx->c, [&] {
     if (k < 1 || k > p->p.n) throw Error(KTH_EINVAL, "k out of range");
+    check_opts(o);
     set_device(p->ctx->c);
     st = three_stage(p->p, k, o, lambda, x, inf);
   });
@@ -288,6 +327,7 @@ kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int
   kth_opts o;
   if (opts) o = *opts; else kth_opts_default(&o);
   return guarded(&ctx->c, [&] {
+    check_opts(o);
     set_device(ctx->c);
     std::vector<Pencil*> ps(np);
     for (int32_t i = 0; i < np; i++) {
@@ -326,6 +366,23 @@ kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t n
       out[5 + 3 * c] = (double)prof.launches[c];
     }
     out[18] = (double)F.hs.neg;
+  });
+}
+
+kth_status kth_debug_mfma_probe_f32(const float* A, const float* B, float* D) {
+  return guarded(nullptr, [&] {
+    float *dA, *dB, *dD;
+    KTH_HIP(hipMalloc(&dA, 64 * sizeof(float)));
+    KTH_HIP(hipMalloc(&dB, 64 * sizeof(float)));
+    KTH_HIP(hipMalloc(&dD, 256 * sizeof(float)));
+    KTH_HIP(hipMemcpy(dA, A, 64 * sizeof(float), hipMemcpyHostToDevice));
+    KTH_HIP(hipMemcpy(dB, B, 64 * sizeof(float), hipMemcpyHostToDevice));
+    launch_mfma_probe_f32(dA, dB, dD, nullptr);
+    KTH_HIP(hipDeviceSynchronize());
+    KTH_HIP(hipMemcpy(D, dD, 256 * sizeof(float), hipMemcpyDeviceToHost));
+    (void)hipFree(dA);
+    (void)hipFree(dB);
+    (void)hipFree(dD);
   });
 }
 

@@ -64,26 +64,31 @@ struct SigmaPack { double v[kMaxBatch]; };
 
 // ---- launchers (factor.hip); nb = number of batched factorizations ---------
 void launch_fill_stats(FactStats* st, int nb, hipStream_t s);
+// T = double (inertia-deciding factors) or float (shift-and-invert factor).
+template <typename T>
 void launch_small_fronts(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t max_nf,
                          const double* aval, const double* bval, const Batch& bt, int nb,
-                         double* L, double* U, double* D, double* E, int32_t* tperm,
+                         T* L, T* U, double* D, double* E, int32_t* tperm,
                          FactStats* st, hipStream_t s);
+template <typename T>
 void launch_front_init(const FrontMeta& M, const Int2* tasks, int32_t count, const double* aval,
-                       const double* bval, const Batch& bt, int nb, double* L, double* U,
-                       hipStream_t s);
+                       const double* bval, const Batch& bt, int nb, T* L, T* U, hipStream_t s);
+template <typename T>
 void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t t,
-                        const Batch& bt, int nb, double* L, double* D, double* E, int32_t* tperm,
-                        double* tinv, FactStats* st, hipStream_t s);
+                        const Batch& bt, int nb, T* L, double* D, double* E, int32_t* tperm,
+                        T* tinv, FactStats* st, hipStream_t s);
+template <typename T>
 void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t,
-                       const Batch& bt, int nb, double* L, double* W, const double* D,
-                       const double* E, const int32_t* tperm, const double* tinv, FactStats* st,
-                       hipStream_t s);
+                       const Batch& bt, int nb, T* L, T* W, const double* D, const double* E,
+                       const int32_t* tperm, const T* tinv, FactStats* st, hipStream_t s);
+template <typename T>
 void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
-                  int32_t nfronts, int32_t ntiles, int32_t t, const Batch& bt, int nb, double* L,
-                  double* U, const double* W, hipStream_t s);
+                  int32_t nfronts, int32_t ntiles, int32_t t, const Batch& bt, int nb, T* L, T* U,
+                  const T* W, hipStream_t s);
 void launch_set_scalar(double* p, double v, hipStream_t s);
 void launch_set_scalars(double* p, int n, const double* values, hipStream_t s);
 // MFMA operand-layout probe (tests only): D = A(16x4) * B(4x16) via one instruction.
 void launch_mfma_probe(const double* A, const double* B, double* D, hipStream_t s);
+void launch_mfma_probe_f32(const float* A, const float* B, float* D, hipStream_t s);
 
 }  // namespace kth

@@ -179,15 +179,126 @@ int64_t nu_checked(Pencil& P, double& sigma, double nudge, Shifts& log, int64_t*
 }  // namespace
 
 void numeric_factor(Pencil& P, NumFactor& F, double sigma, kth_precision prec) {
-  if (prec != KTH_FP64) throw Error(KTH_EINVAL, "only FP64 factors are available in this build");
-  factor_alloc(P, F);
-  F.prec = prec;
+  if (prec != KTH_FP64 && prec != KTH_FP32_IR) throw Error(KTH_EINVAL, "unknown precision");
+  factor_alloc(P, F, 1, prec);
   factor_enqueue(P, F, sigma, false);
   factor_read_stats(P, F);
 }
 
+SolveOutcome solve_refined(Pencil& P, NumFactor& F, const double* b, double* x, double tol) {
+  SolveOutcome out;
+  solve_enqueue_f(P, F, b, x);
+  if (F.prec == KTH_FP64) return out;
+  Ctx* c = P.ctx;
+  hipStream_t st = c->stream;
+  const int64_t n = P.n;
+  const int mk = kGmresMax;
+  if (!F.ir_r.p) {
+    F.ir_r.alloc(c, n);
+    F.ir_V.alloc(c, (size_t)n * (mk + 1));
+    F.ir_part.alloc(c, (size_t)multidot_blocks(n) * (mk + 1));
+    F.ir_out.alloc(c, 2 * (mk + 1) + 4);
+  }
+  double* r = F.ir_r.get();
+  double* V = F.ir_V.get();
+  double* part = F.ir_part.get();
+  double* h1 = F.ir_out.get();            // [mk + 1]
+  double* h2 = h1 + (mk + 1);             // [mk + 1]
+  double* nrm = h2 + (mk + 1);            // [4]: ||r||_inf, ||x||_inf, ||b||_inf, ||w||_2^2
+  auto col = [&](int j) { return V + (size_t)j * n; };
+  auto norm2sq = [&](const double* v) {
+    multidot(n, 1, v, n, v, part, nrm + 3, 1.0, st);
+    double t;
+    d2h(c, &t, nrm + 3, 1);
+    return t;
+  };
+  // ||A - sigma B||_inf bounded by ||A||_inf + |sigma| ||B||_inf
+  const double normM = P.normA_inf + std::fabs(F.sigma) * P.normB_inf;
+  const double* A = P.aval.get();
+  const double* Bv = P.bval.get();
+  absmax(n, b, part, nrm + 2, st);
+  double prev = INFINITY;
+  int slow = 0;
+  std::vector<double> y(mk);   // outlives the asynchronous upload below
+  for (int outer = 0;; outer++) {
+    shifted_residual(n, P.rowptr.get(), P.col.get(), A, Bv, F.sigma, x, b, r, st);
+    absmax(n, r, part, nrm, st);
+    absmax(n, x, part, nrm + 1, st);
+    double hn[3];
+    d2h(c, hn, nrm, 3);
+    const double den = normM * hn[1] + hn[2];
+    out.berr = den > 0 ? hn[0] / den : 0.0;
+    if (!std::isfinite(out.berr)) { out.converged = false; return out; }
+    if (out.berr <= tol) return out;
+    if (hn[0] > 0.5 * prev) {
+      if (++slow >= 2) { out.converged = false; return out; }
+    } else {
+      slow = 0;
+    }
+    if (outer >= kIrMaxOuter) { out.converged = false; return out; }
+    prev = hn[0];
+    // GMRES on M32^{-1} M d = M32^{-1} r from d = 0 (CGS2 Arnoldi, Givens QR of H)
+    solve_enqueue_f(P, F, r, col(0));
+    out.steps++;
+    const double beta = std::sqrt(norm2sq(col(0)));
+    if (!(beta > 0) || !std::isfinite(beta)) { out.converged = false; return out; }
+    scale_copy(n, 1.0 / beta, col(0), col(0), st);
+    std::vector<double> H((size_t)(mk + 1) * mk, 0.0), cs(mk), sn(mk), g(mk + 1, 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < mk; j++) {
+      // w = M32^{-1} (M v_j), stored in column j + 1
+      shifted_residual(n, P.rowptr.get(), P.col.get(), A, Bv, F.sigma, col(j), nullptr, r, st);
+      solve_enqueue_f(P, F, r, col(j + 1));
+      out.steps++;
+      double* w = col(j + 1);
+      multidot(n, j + 1, V, n, w, part, h1, 1.0, st);
+      multiaxpy(n, j + 1, V, n, h1, w, nullptr, nullptr, st);
+      multidot(n, j + 1, V, n, w, part, h2, 1.0, st);
+      multiaxpy(n, j + 1, V, n, h2, w, nullptr, nullptr, st);
+      std::vector<double> ha(j + 1), hb(j + 1);
+      d2h(c, ha.data(), h1, j + 1);
+      d2h(c, hb.data(), h2, j + 1);
+      const double hw = std::sqrt(std::max(norm2sq(w), 0.0));
+      double* hc = &H[(size_t)j * (mk + 1)];
+      for (int i = 0; i <= j; i++) hc[i] = ha[i] + hb[i];
+      hc[j + 1] = hw;
+      if (hw > 0) scale_copy(n, 1.0 / hw, w, w, st);
+      for (int i = 0; i < j; i++) {   // earlier rotations
+        const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+        hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+        hc[i] = t;
+      }
+      const double rho = std::hypot(hc[j], hc[j + 1]);
+      cs[j] = rho > 0 ? hc[j] / rho : 1.0;
+      sn[j] = rho > 0 ? hc[j + 1] / rho : 0.0;
+      hc[j] = rho;
+      hc[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      if (std::fabs(g[j + 1]) <= kGmresTol * beta || !(hw > 0)) break;
+    }
+    // y = R^{-1} g, x += V y  (as x -= V (-y))
+    for (int i = k - 1; i >= 0; i--) {
+      double t = g[i];
+      for (int q = i + 1; q < k; q++) t -= H[(size_t)q * (mk + 1) + i] * y[q];
+      const double d = H[(size_t)i * (mk + 1) + i];
+      y[i] = d != 0 ? t / d : 0.0;
+    }
+    for (int i = 0; i < k; i++) y[i] = -y[i];
+    h2d(c, h1, y.data(), k);
+    multiaxpy(n, k, V, n, h1, x, nullptr, nullptr, st);
+  }
+}
+
 void solve_many(Pencil& P, NumFactor& F, int32_t nrhs, const double* r, int64_t ldr, double* x,
-                int64_t ldx, bool device_ptrs) {
+                int64_t ldx, bool device_ptrs, bool unrefined) {
+  auto one = [&](const double* b, double* xx) {
+    if (!unrefined) return solve_refined(P, F, b, xx);
+    solve_enqueue_f(P, F, b, xx);
+    return SolveOutcome{};
+  };
   Ctx* c = P.ctx;
   DBuf<double> rb, xb;
   if (!device_ptrs) {
@@ -197,12 +308,18 @@ void solve_many(Pencil& P, NumFactor& F, int32_t nrhs, const double* r, int64_t 
   for (int32_t q = 0; q < nrhs; q++) {
     const double* rq = r + (size_t)q * ldr;
     double* xq = x + (size_t)q * ldx;
+    SolveOutcome so;
     if (device_ptrs) {
-      solve_enqueue_f(P, F, rq, xq);
+      so = one(rq, xq);
     } else {
       h2d(c, rb.get(), rq, P.n);
-      solve_enqueue_f(P, F, rb.get(), xb.get());
+      so = one(rb.get(), xb.get());
       d2h(c, xq, xb.get(), P.n);
+    }
+    if (!so.converged) {
+      c->sync();
+      throw Error(KTH_ENOCONV, "iterative refinement of the FP32 factor stalled at backward error " +
+                                   std::to_string(so.berr) + " (column " + std::to_string(q) + ")");
     }
   }
   c->sync();
@@ -383,17 +500,25 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   double sigma = 0.5 * (sl + su);
   double tsi = now_s();
   NumFactor FS;
-  factor_alloc(P, FS);
-  for (int attempt = 0;; attempt++) {
-    factor_enqueue(P, FS, sigma, false);
-    factor_read_stats(P, FS);
-    nfac++;
-    if (FS.hs.zero == 0) break;
-    if (attempt > 6) throw Error(KTH_ESINGULAR, "shift-and-invert factor keeps hitting zero pivots");
-    sigma += 1e-3 * (su - sl);
-  }
-  if ((int64_t)FS.hs.neg < nl || (int64_t)FS.hs.neg > nu_)
-    throw Error(KTH_EDEVICE, "inertia at the interval midpoint is outside [nu_l, nu_u]");
+  // the shift-and-invert factor: FP64, or FP32 with FP64 refinement of every solve
+  // (falls back to FP64 at the same shift if a refinement stalls)
+  auto si_factor = [&](kth_precision prec) {
+    factor_alloc(P, FS, 1, prec);
+    for (int attempt = 0;; attempt++) {
+      factor_enqueue(P, FS, sigma, false);
+      factor_read_stats(P, FS);
+      nfac++;
+      if (FS.hs.zero == 0) break;
+      if (attempt > 6) throw Error(KTH_ESINGULAR, "shift-and-invert factor keeps hitting zero pivots");
+      sigma += 1e-3 * (su - sl);
+    }
+    // the FP64 count is exact; the FP32 one only serves the factor itself
+    if (prec == KTH_FP64 && ((int64_t)FS.hs.neg < nl || (int64_t)FS.hs.neg > nu_))
+      throw Error(KTH_EDEVICE, "inertia at the interval midpoint is outside [nu_l, nu_u]");
+  };
+  si_factor(o.si_precision == KTH_FP32_IR ? KTH_FP32_IR : KTH_FP64);
+  int ir_steps = 0, ir_fallback = 0;
+  double ir_max_berr = 0;
   t_task[5] = now_s() - tsi;
   double t3 = now_s();
   start_vec(1, hv);
@@ -413,7 +538,23 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   for (int j = 1; j <= o.max_lanczos; j++) {
     W.ensure_cols(j + 1);
     // w = (A - sigma B)^{-1} v~_j, Bw = B w
-    solve_enqueue_f(P, FS, W.vt(j - 1), W.w.get());
+    {
+      SolveOutcome so = solve_refined(P, FS, W.vt(j - 1), W.w.get(), o.ir_tol > 0 ? o.ir_tol : kIrTol);
+      if (!so.converged) {
+        // refinement stalled: refactor in FP64 at the same shift and redo this solve
+        const double ts = now_s();
+        const double sig_keep = sigma;
+        si_factor(KTH_FP64);
+        if (sigma != sig_keep)
+          throw Error(KTH_ESINGULAR, "FP64 fallback factor hit a zero pivot at the FP32 shift");
+        t_task[5] += now_s() - ts;
+        ir_fallback = 1;
+        solve_enqueue_f(P, FS, W.vt(j - 1), W.w.get());
+      } else {
+        ir_steps += so.steps;
+        ir_max_berr = std::max(ir_max_berr, so.berr);
+      }
+    }
     spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.w.get(), nullptr, W.Bw.get(), st);
     // CGS2 in the B inner product: h = V~^T w = V^T B w
     multidot(n, j, W.Vt.get(), n, W.w.get(), W.partial.get(), W.h.get(), 1.0, st);
@@ -555,6 +696,10 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
     info->sigmas[q] = log.s[q];
     info->nus[q] = log.nu[q];
   }
+  info->si_precision = FS.prec;
+  info->ir_steps = ir_steps;
+  info->ir_fallback = ir_fallback;
+  info->ir_max_berr = ir_max_berr;
   if (result != KTH_OK) {
     c->last_error = result == KTH_ECLUSTER ? "error bounds never became disjoint"
                                            : "shift-and-invert Lanczos did not converge";

@@ -247,12 +247,14 @@ static void ensure_workspace(Pencil& P, int nb) {
   P.ws_batches = nb;
 }
 
-void factor_alloc(Pencil& P, NumFactor& F, int nb) {
+void factor_alloc(Pencil& P, NumFactor& F, int nb, kth_precision prec) {
   Ctx* c = P.ctx;
   if (nb < 1 || nb > kMaxBatch) throw Error(KTH_EINVAL, "batch of factorizations out of range");
   F.p = &P;
   F.nb = nb;
-  F.L.alloc(c, (size_t)P.S.lptr[P.S.nsup] * nb);
+  F.prec = prec;
+  const size_t lsz = (size_t)P.S.lptr[P.S.nsup] * nb;
+  F.L.alloc(c, prec == KTH_FP64 ? lsz : (lsz + 1) / 2);   // float panels in the same buffer type
   F.D.alloc(c, (size_t)P.n * nb);
   F.E.alloc(c, (size_t)P.n * nb);
   F.tperm.alloc(c, (size_t)P.n * nb);
@@ -306,8 +308,9 @@ void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b, FactorPr
   factor_enqueue_batch(P, F, &sigma, 1, mode_b, prof);
 }
 
-void factor_enqueue_batch(Pencil& P, NumFactor& F, const double* sigmas, int nb, bool mode_b,
-                          FactorProfile* prof) {
+template <typename T>
+static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int nb, bool mode_b,
+                             FactorProfile* prof) {
   Ctx* c = P.ctx;
   hipStream_t st = c->stream;
   const Symbolic& S = P.S;
@@ -329,6 +332,10 @@ void factor_enqueue_batch(Pencil& P, NumFactor& F, const double* sigmas, int nb,
   bt.sN = P.n;
   bt.sig = F.sig.get();
   const int32_t* sched = P.d_sched.get();
+  T* Lf = reinterpret_cast<T*>(F.L.get());
+  T* Uf = reinterpret_cast<T*>(P.U.get());
+  T* Wf = reinterpret_cast<T*>(P.W.get());
+  T* Tf = reinterpret_cast<T*>(P.Tinv.get());
   const std::vector<int32_t>& hs = P.h_sched;
   for (const LevelPlan& lp : P.levels) {
     if (lp.small_cnt > 0) {
@@ -340,14 +347,14 @@ void factor_enqueue_batch(Pencil& P, NumFactor& F, const double* sigmas, int nb,
         }
       ProfScope ps(prof, st, PROF_SMALL, fl);
       launch_small_fronts(P.meta, sched + lp.small_off, lp.small_cnt, lp.small_maxnf, av, bv, bt,
-                          nb, F.L.get(), P.U.get(), F.D.get(), F.E.get(), F.tperm.get(),
+                          nb, Lf, Uf, F.D.get(), F.E.get(), F.tperm.get(),
                           F.stats.get(), st);
     }
     if (lp.large_cnt == 0) continue;
     {
       ProfScope ps(prof, st, PROF_INIT, 0.0);
       launch_front_init(P.meta, reinterpret_cast<const Int2*>(sched + lp.init_off), lp.init_cnt, av,
-                        bv, bt, nb, F.L.get(), P.U.get(), st);
+                        bv, bt, nb, Lf, Uf, st);
     }
     for (const StepPlan& sp : lp.steps) {
       double fl_tile = 0, fl_trsm = 0, fl_schur = 0;
@@ -363,23 +370,29 @@ void factor_enqueue_batch(Pencil& P, NumFactor& F, const double* sigmas, int nb,
         }
       {
         ProfScope ps(prof, st, PROF_TILE, fl_tile);
-        launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, bt, nb, F.L.get(),
-                           F.D.get(), F.E.get(), F.tperm.get(), P.Tinv.get(), F.stats.get(), st);
+        launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, bt, nb, Lf,
+                           F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), st);
       }
       {
         ProfScope ps(prof, st, PROF_TRSM, fl_trsm);
         launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm_off), sp.trsm_cnt,
-                          sp.t, bt, nb, F.L.get(), P.W.get(), F.D.get(), F.E.get(), F.tperm.get(),
-                          P.Tinv.get(), F.stats.get(), st);
+                          sp.t, bt, nb, Lf, Wf, F.D.get(), F.E.get(), F.tperm.get(),
+                          Tf, F.stats.get(), st);
       }
       {
         ProfScope ps(prof, st, PROF_SCHUR, fl_schur);
         launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
-                     sp.t, bt, nb, F.L.get(), P.U.get(), P.W.get(), st);
+                     sp.t, bt, nb, Lf, Uf, Wf, st);
       }
     }
   }
   KTH_HIP(hipGetLastError());
+}
+
+void factor_enqueue_batch(Pencil& P, NumFactor& F, const double* sigmas, int nb, bool mode_b,
+                          FactorProfile* prof) {
+  if (F.prec == KTH_FP64) factor_enqueue_t<double>(P, F, sigmas, nb, mode_b, prof);
+  else factor_enqueue_t<float>(P, F, sigmas, nb, mode_b, prof);
 }
 
 void factor_profile_finish(Pencil& P, FactorProfile& prof) {
@@ -421,9 +434,14 @@ void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x) {
     F.R.alloc(c, P.S.rows.size());
     F.partial.alloc(c, (size_t)P.splan.partial_size);
   }
-  solve_enqueue<double>(P.splan, P.meta, F.L.get(), F.D.get(), F.E.get(), F.tperm.get(),
-                        P.d_perm.get(), P.n, b, x, F.xe.get(), F.ye.get(), F.R.get(),
-                        F.partial.get(), c->stream);
+  if (F.prec == KTH_FP64)
+    solve_enqueue<double>(P.splan, P.meta, F.L.get(), F.D.get(), F.E.get(), F.tperm.get(),
+                          P.d_perm.get(), P.n, b, x, F.xe.get(), F.ye.get(), F.R.get(),
+                          F.partial.get(), c->stream);
+  else
+    solve_enqueue<float>(P.splan, P.meta, reinterpret_cast<const float*>(F.L.get()), F.D.get(),
+                         F.E.get(), F.tperm.get(), P.d_perm.get(), P.n, b, x, F.xe.get(),
+                         F.ye.get(), F.R.get(), F.partial.get(), c->stream);
 }
 
 }  // namespace kth

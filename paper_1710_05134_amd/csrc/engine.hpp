@@ -137,6 +137,8 @@ struct NumFactor {
   bool have_stats = false;
   // solve scratch
   DBuf<double> xe, ye, R, partial;
+  // refinement scratch (FP32 factors): residual, Krylov basis, dot partials, small results
+  DBuf<double> ir_r, ir_V, ir_part, ir_out;
 };
 
 // Per-kernel-class timing of one factorization (HIP events on the context stream).
@@ -154,7 +156,7 @@ struct FactorProfile {
 void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
                  const double* a, const double* b, uint32_t flags);
 void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_ptrs);
-void factor_alloc(Pencil& P, NumFactor& F, int nb = 1);
+void factor_alloc(Pencil& P, NumFactor& F, int nb = 1, kth_precision prec = KTH_FP64);
 // Largest batch of factorizations that fits in free device memory (<= cap).
 int factor_batch_capacity(Pencil& P, int cap);
 // Enqueue the numeric factorization of A - sigma B (mode_b: factor B itself).

@@ -66,19 +66,19 @@ __device__ inline double block_max(double v, double* sv) {
 }
 
 // Symmetric interchange of rows/columns k < r of a lower-stored LDS matrix.
-template <int NT>
-__device__ inline void lds_sym_swap(double* F, int ld, int nrows, int k, int r) {
+template <int NT, typename T>
+__device__ inline void lds_sym_swap(T* F, int ld, int nrows, int k, int r) {
   // tasks: [0,k): columns left of k;  k: diagonal;  (k,r): the band between;  (r,nrows): below r
   for (int x = threadIdx.x; x < nrows - 1; x += NT) {
     if (x < k) {
-      double t = F[k + x * ld]; F[k + x * ld] = F[r + x * ld]; F[r + x * ld] = t;
+      T t = F[k + x * ld]; F[k + x * ld] = F[r + x * ld]; F[r + x * ld] = t;
     } else if (x == k) {
-      double t = F[k + k * ld]; F[k + k * ld] = F[r + r * ld]; F[r + r * ld] = t;
+      T t = F[k + k * ld]; F[k + k * ld] = F[r + r * ld]; F[r + r * ld] = t;
     } else if (x < r) {
-      double t = F[x + k * ld]; F[x + k * ld] = F[r + x * ld]; F[r + x * ld] = t;
+      T t = F[x + k * ld]; F[x + k * ld] = F[r + x * ld]; F[r + x * ld] = t;
     } else {
       int i = x + 1;
-      double t = F[i + k * ld]; F[i + k * ld] = F[i + r * ld]; F[i + r * ld] = t;
+      T t = F[i + k * ld]; F[i + k * ld] = F[i + r * ld]; F[i + r * ld] = t;
     }
   }
 }
@@ -94,9 +94,9 @@ struct BKCounts {
 // complement).  lp[] receives the pivot order, d[]/e[] the blocks of D.
 // On return F holds unit-lower L in the eliminated columns and the Schur
 // complement in the trailing block.  Counts accumulate in thread 0's cnt.
-template <int NT>
-__device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, double* d,
-                              double* e, double* lcol, BKCounts& cnt, double* sv, int* si) {
+template <int NT, typename T>
+__device__ void bk_factor_lds(T* F, int ld, int nrows, int ncand, int* lp, T* d,
+                              T* e, T* lcol, BKCounts& cnt, double* sv, int* si) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
   double maxl = 0.0;
@@ -112,7 +112,7 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
       // 128 - row, so ties go to the smaller row; key 0 = no candidate)
       unsigned long long key = 0;
       for (int i = k + 1 + tid; i < ncand; i += NT) {
-        unsigned long long kk2 = (dbits(fabs(F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
+        unsigned long long kk2 = (dbits(fabs((double)F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
         key = kk2 > key ? kk2 : key;
       }
       for (int off = 32; off > 0; off >>= 1) {
@@ -120,48 +120,48 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
         key = o > key ? o : key;
       }
       if (key == 0) { r = k; g1 = 0.0; }
-      else { r = 128 - (int)(key & 0xFFull); g1 = fabs(F[r + k * ld]); }
+      else { r = 128 - (int)(key & 0xFFull); g1 = fabs((double)F[r + k * ld]); }
     } else {
       double v = -1.0;
       int idx = -1;
       for (int i = k + 1 + tid; i < ncand; i += NT) {
-        double x = fabs(F[i + k * ld]);
+        double x = fabs((double)F[i + k * ld]);
         if (x > v) { v = x; idx = i; }
       }
       block_argmax<NT>(v, idx, sv, si);
       g1 = idx < 0 ? 0.0 : v;
       r = idx < 0 ? k : idx;
     }
-    const double akk = fabs(F[k + k * ld]);
+    const double akk = fabs((double)F[k + k * ld]);
     int kind = 0;  // 0: 1x1 at k; 1: 1x1 at r (swap k,r); 2: 2x2 (k, r -> k+1)
     if (!(g1 == 0.0 || akk >= kAlphaBK * g1)) {
       double gv = 0.0;
       for (int i = k + tid; i < ncand; i += NT) {
         if (i == r) continue;
-        double x = i < r ? fabs(F[r + i * ld]) : fabs(F[i + r * ld]);
+        double x = i < r ? fabs((double)F[r + i * ld]) : fabs((double)F[i + r * ld]);
         gv = fmax(gv, x);
       }
       const double gr = block_max<NT>(gv, sv);
       if (akk * gr >= kAlphaBK * g1 * g1) kind = 0;
-      else if (fabs(F[r + r * ld]) >= kAlphaBK * gr) kind = 1;
+      else if (fabs((double)F[r + r * ld]) >= kAlphaBK * gr) kind = 1;
       else kind = 2;
     }
     __syncthreads();  // every thread has read the pivot candidates before any swap
     if (kind == 1) {
-      lds_sym_swap<NT>(F, ld, nrows, k, r);
+      lds_sym_swap<NT, T>(F, ld, nrows, k, r);
       if (tid == 0) { int t = lp[k]; lp[k] = lp[r]; lp[r] = t; }
       __syncthreads();
     } else if (kind == 2 && r != k + 1) {
-      lds_sym_swap<NT>(F, ld, nrows, k + 1, r);
+      lds_sym_swap<NT, T>(F, ld, nrows, k + 1, r);
       if (tid == 0) { int t = lp[k + 1]; lp[k + 1] = lp[r]; lp[r] = t; }
       __syncthreads();
     }
     if (kind < 2) {
-      const double dk = F[k + k * ld];
+      const T dk = F[k + k * ld];
       if (tid == 0) {
         d[k] = dk; e[k] = 0.0;
         if (dk < 0) cnt.neg++; else if (dk > 0) cnt.pos++; else cnt.zero++;
-        cnt.mind = fmin(cnt.mind, fabs(dk));
+        cnt.mind = fmin(cnt.mind, fabs((double)dk));
       }
       if (dk != 0.0) {
         for (int i = k + 1 + tid; i < nrows; i += NT) lcol[i] = F[i + k * ld] / dk;
@@ -171,13 +171,13 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
           // group are issued before the stores of the current one (no aliasing: other j)
           const int i = lane;
           if (i > k && i < nrows) {
-            const double li = lcol[i];
+            const T li = lcol[i];
             int j = k + 1;
             if (j + 3 <= i) {
-              double c0 = F[j + k * ld], c1 = F[j + 1 + k * ld], c2 = F[j + 2 + k * ld], c3 = F[j + 3 + k * ld];
-              double a0 = F[i + j * ld], a1 = F[i + (j + 1) * ld], a2 = F[i + (j + 2) * ld], a3 = F[i + (j + 3) * ld];
+              T c0 = F[j + k * ld], c1 = F[j + 1 + k * ld], c2 = F[j + 2 + k * ld], c3 = F[j + 3 + k * ld];
+              T a0 = F[i + j * ld], a1 = F[i + (j + 1) * ld], a2 = F[i + (j + 2) * ld], a3 = F[i + (j + 3) * ld];
               for (;;) {
-                const double r0 = a0 - li * c0, r1 = a1 - li * c1, r2 = a2 - li * c2, r3 = a3 - li * c3;
+                const T r0 = a0 - li * c0, r1 = a1 - li * c1, r2 = a2 - li * c2, r3 = a3 - li * c3;
                 const int jn = j + 4;
                 const bool more = jn + 3 <= i;
                 if (more) {
@@ -196,14 +196,14 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
           }
         } else {
           for (int j = k + 1 + wave; j < nrows; j += NW) {
-            const double fj = F[j + k * ld];
+            const T fj = F[j + k * ld];
             for (int i = j + lane; i < nrows; i += 64) F[i + j * ld] -= lcol[i] * fj;
           }
         }
         __syncthreads();
         for (int i = k + 1 + tid; i < nrows; i += NT) {
           F[i + k * ld] = lcol[i];
-          maxl = fmax(maxl, fabs(lcol[i]));
+          maxl = fmax(maxl, fabs((double)lcol[i]));
         }
       } else {
         for (int i = k + 1 + tid; i < nrows; i += NT) F[i + k * ld] = 0.0;
@@ -212,21 +212,21 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
       __syncthreads();
       k += 1;
     } else {
-      const double a = F[k + k * ld], b = F[(k + 1) + k * ld], c = F[(k + 1) + (k + 1) * ld];
-      const double det = a * c - b * b;
+      const T a = F[k + k * ld], b = F[(k + 1) + k * ld], c = F[(k + 1) + (k + 1) * ld];
+      const T det = a * c - b * b;
       if (tid == 0) {
         d[k] = a; e[k] = b; d[k + 1] = c; e[k + 1] = 0.0;
-        const double tr = a + c;
+        const T tr = a + c;
         if (det < 0) { cnt.neg++; cnt.pos++; }
         else if (det > 0) { if (tr < 0) cnt.neg += 2; else cnt.pos += 2; }
         else { cnt.zero++; if (tr < 0) cnt.neg++; else if (tr > 0) cnt.pos++; else cnt.zero++; }
         cnt.n2x2++;
-        const double m = 0.5 * tr, q = sqrt(0.25 * (a - c) * (a - c) + b * b);
-        cnt.mind = fmin(cnt.mind, fmin(fabs(m - q), fabs(m + q)));
+        const T m = 0.5 * tr, q = sqrt(0.25 * (a - c) * (a - c) + b * b);
+        cnt.mind = fmin(cnt.mind, fmin(fabs((double)m - q), fabs((double)m + q)));
       }
-      double* lcol2 = lcol + ld;
+      T* lcol2 = lcol + ld;
       for (int i = k + 2 + tid; i < nrows; i += NT) {
-        const double w1 = F[i + k * ld], w2 = F[i + (k + 1) * ld];
+        const T w1 = F[i + k * ld], w2 = F[i + (k + 1) * ld];
         lcol[i] = (c * w1 - b * w2) / det;
         lcol2[i] = (a * w2 - b * w1) / det;
       }
@@ -234,12 +234,12 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
       if constexpr (NT == 64) {
         const int i = lane;
         if (i > k + 1 && i < nrows) {
-          const double l1 = lcol[i], l2 = lcol2[i];
+          const T l1 = lcol[i], l2 = lcol2[i];
           int j = k + 2;
           for (; j + 1 <= i; j += 2) {
-            const double w10 = F[j + k * ld], w20 = F[j + (k + 1) * ld];
-            const double w11 = F[j + 1 + k * ld], w21 = F[j + 1 + (k + 1) * ld];
-            const double a0 = F[i + j * ld], a1 = F[i + (j + 1) * ld];
+            const T w10 = F[j + k * ld], w20 = F[j + (k + 1) * ld];
+            const T w11 = F[j + 1 + k * ld], w21 = F[j + 1 + (k + 1) * ld];
+            const T a0 = F[i + j * ld], a1 = F[i + (j + 1) * ld];
             F[i + j * ld] = a0 - (l1 * w10 + l2 * w20);
             F[i + (j + 1) * ld] = a1 - (l1 * w11 + l2 * w21);
           }
@@ -247,7 +247,7 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
         }
       } else {
         for (int j = k + 2 + wave; j < nrows; j += NW) {
-          const double w1 = F[j + k * ld], w2 = F[j + (k + 1) * ld];
+          const T w1 = F[j + k * ld], w2 = F[j + (k + 1) * ld];
           for (int i = j + lane; i < nrows; i += 64) F[i + j * ld] -= lcol[i] * w1 + lcol2[i] * w2;
         }
       }
@@ -255,7 +255,7 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
       for (int i = k + 2 + tid; i < nrows; i += NT) {
         F[i + k * ld] = lcol[i];
         F[i + (k + 1) * ld] = lcol2[i];
-        maxl = fmax(maxl, fmax(fabs(lcol[i]), fabs(lcol2[i])));
+        maxl = fmax(maxl, fmax(fabs((double)lcol[i]), fabs((double)lcol2[i])));
       }
       if (tid == 0) { F[k + k * ld] = 1.0; F[(k + 1) + k * ld] = 0.0; F[(k + 1) + (k + 1) * ld] = 1.0; }
       __syncthreads();
@@ -269,8 +269,9 @@ __device__ void bk_factor_lds(double* F, int ld, int nrows, int ncand, int* lp, 
 // Bunch-Kaufman LDL^T of one kb x kb pivot tile (kb <= kNB) in LDS, by 4 wavefronts:
 // wave 0 searches pivots (lanes = rows, shuffle reductions), every wave updates a
 // quarter of the columns of each row (lane = row, wave = column residue mod 4).
-__device__ void bk_tile_lds(double* F, int ld, int kb, int* lp, double* d, double* e,
-                            double* lcol, BKCounts& cnt, int* dec) {
+template <typename T>
+__device__ void bk_tile_lds(T* F, int ld, int kb, int* lp, T* d, T* e,
+                            T* lcol, BKCounts& cnt, int* dec) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double maxl = 0.0;
   if (tid < kNB) lp[tid] = tid;
@@ -282,21 +283,21 @@ __device__ void bk_tile_lds(double* F, int ld, int kb, int* lp, double* d, doubl
       unsigned long long key = 0;
       const int i = lane;
       if (i > k && i < kb)
-        key = (dbits(fabs(F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
+        key = (dbits(fabs((double)F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
       for (int off = 32; off > 0; off >>= 1) {
         unsigned long long o = __shfl_xor(key, off);
         key = o > key ? o : key;
       }
       const int r = key == 0 ? k : 128 - (int)(key & 0xFFull);
-      const double g1 = key == 0 ? 0.0 : fabs(F[r + k * ld]);
-      const double akk = fabs(F[k + k * ld]);
+      const double g1 = key == 0 ? 0.0 : fabs((double)F[r + k * ld]);
+      const double akk = fabs((double)F[k + k * ld]);
       int kind = 0;
       if (!(g1 == 0.0 || akk >= kAlphaBK * g1)) {
         double gv = 0.0;
-        if (i >= k && i < kb && i != r) gv = i < r ? fabs(F[r + i * ld]) : fabs(F[i + r * ld]);
+        if (i >= k && i < kb && i != r) gv = i < r ? fabs((double)F[r + i * ld]) : fabs((double)F[i + r * ld]);
         for (int off = 32; off > 0; off >>= 1) gv = fmax(gv, __shfl_xor(gv, off));
         if (akk * gv >= kAlphaBK * g1 * g1) kind = 0;
-        else if (fabs(F[r + r * ld]) >= kAlphaBK * gv) kind = 1;
+        else if (fabs((double)F[r + r * ld]) >= kAlphaBK * gv) kind = 1;
         else kind = 2;
       }
       if (lane == 0) { dec[0] = kind; dec[1] = r; }
@@ -305,50 +306,50 @@ __device__ void bk_tile_lds(double* F, int ld, int kb, int* lp, double* d, doubl
     const int kind = dec[0], r = dec[1];
     if (kind == 1 || (kind == 2 && r != k + 1)) {
       const int a = kind == 1 ? k : k + 1;
-      lds_sym_swap<256>(F, ld, kb, a, r);
+      lds_sym_swap<256, T>(F, ld, kb, a, r);
       if (tid == 0) { int t = lp[a]; lp[a] = lp[r]; lp[r] = t; }
       __syncthreads();
     }
     if (kind < 2) {
-      const double dk = F[k + k * ld];
+      const T dk = F[k + k * ld];
       if (tid == 0) {
         d[k] = dk; e[k] = 0.0;
         if (dk < 0) cnt.neg++; else if (dk > 0) cnt.pos++; else cnt.zero++;
-        cnt.mind = fmin(cnt.mind, fabs(dk));
+        cnt.mind = fmin(cnt.mind, fabs((double)dk));
       }
       if (wave == 0 && lane > k && lane < kb) lcol[lane] = dk != 0.0 ? F[lane + k * ld] / dk : 0.0;
       __syncthreads();
       if (dk != 0.0) {
         const int i = lane;
         if (i > k && i < kb) {
-          const double li = lcol[i];
+          const T li = lcol[i];
           for (int j = k + 1 + wave; j <= i; j += 4) F[i + j * ld] -= li * F[j + k * ld];
         }
       }
       __syncthreads();
       if (wave == 0 && lane > k && lane < kb) {
         F[lane + k * ld] = lcol[lane];
-        maxl = fmax(maxl, fabs(lcol[lane]));
+        maxl = fmax(maxl, fabs((double)lcol[lane]));
       }
       if (tid == 0) F[k + k * ld] = 1.0;
       __syncthreads();
       k += 1;
     } else {
-      const double a = F[k + k * ld], b = F[(k + 1) + k * ld], c = F[(k + 1) + (k + 1) * ld];
-      const double det = a * c - b * b;
+      const T a = F[k + k * ld], b = F[(k + 1) + k * ld], c = F[(k + 1) + (k + 1) * ld];
+      const T det = a * c - b * b;
       if (tid == 0) {
         d[k] = a; e[k] = b; d[k + 1] = c; e[k + 1] = 0.0;
-        const double tr = a + c;
+        const T tr = a + c;
         if (det < 0) { cnt.neg++; cnt.pos++; }
         else if (det > 0) { if (tr < 0) cnt.neg += 2; else cnt.pos += 2; }
         else { cnt.zero++; if (tr < 0) cnt.neg++; else if (tr > 0) cnt.pos++; else cnt.zero++; }
         cnt.n2x2++;
-        const double m = 0.5 * tr, q = sqrt(0.25 * (a - c) * (a - c) + b * b);
-        cnt.mind = fmin(cnt.mind, fmin(fabs(m - q), fabs(m + q)));
+        const T m = 0.5 * tr, q = sqrt(0.25 * (a - c) * (a - c) + b * b);
+        cnt.mind = fmin(cnt.mind, fmin(fabs((double)m - q), fabs((double)m + q)));
       }
-      double* lcol2 = lcol + kNB;
+      T* lcol2 = lcol + kNB;
       if (wave == 0 && lane > k + 1 && lane < kb) {
-        const double w1 = F[lane + k * ld], w2 = F[lane + (k + 1) * ld];
+        const T w1 = F[lane + k * ld], w2 = F[lane + (k + 1) * ld];
         lcol[lane] = (c * w1 - b * w2) / det;
         lcol2[lane] = (a * w2 - b * w1) / det;
       }
@@ -356,7 +357,7 @@ __device__ void bk_tile_lds(double* F, int ld, int kb, int* lp, double* d, doubl
       {
         const int i = lane;
         if (i > k + 1 && i < kb) {
-          const double l1 = lcol[i], l2 = lcol2[i];
+          const T l1 = lcol[i], l2 = lcol2[i];
           for (int j = k + 2 + wave; j <= i; j += 4)
             F[i + j * ld] -= l1 * F[j + k * ld] + l2 * F[j + (k + 1) * ld];
         }
@@ -365,7 +366,7 @@ __device__ void bk_tile_lds(double* F, int ld, int kb, int* lp, double* d, doubl
       if (wave == 0 && lane > k + 1 && lane < kb) {
         F[lane + k * ld] = lcol[lane];
         F[lane + (k + 1) * ld] = lcol2[lane];
-        maxl = fmax(maxl, fmax(fabs(lcol[lane]), fabs(lcol2[lane])));
+        maxl = fmax(maxl, fmax(fabs((double)lcol[lane]), fabs((double)lcol2[lane])));
       }
       if (tid == 0) { F[k + k * ld] = 1.0; F[(k + 1) + k * ld] = 0.0; F[(k + 1) + (k + 1) * ld] = 1.0; }
       __syncthreads();
@@ -399,23 +400,24 @@ __global__ void k_fill_stats(FactStats* st) {
 // ---------------------------------------------------------------------------
 // Small fronts: everything in LDS.
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_small_fronts(FrontMeta M, const int32_t* fronts,
                                                      const double* __restrict__ aval,
                                                      const double* __restrict__ bval,
-                                                     Batch bt, double* L, double* U,
+                                                     Batch bt, T* L, T* U,
                                                      double* D, double* E, int32_t* tperm,
                                                      FactStats* st) {
   const int64_t bidx = blockIdx.y;
   L += bidx * bt.sL; U += bidx * bt.sU; D += bidx * bt.sN; E += bidx * bt.sN;
   tperm += bidx * bt.sN; st += bidx;
   const double* sigma_dev = bt.sig + bidx;
-  extern __shared__ double smem[];
+  extern __shared__ unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
   __shared__ double sv[NT / 64];
   __shared__ int si[NT / 64];
   __shared__ int lp[kSmallMaxNf];
-  __shared__ double dd[kSmallMaxNf], ee[kSmallMaxNf];
-  __shared__ double lcol[2 * kSmallMaxNf];
+  __shared__ T dd[kSmallMaxNf], ee[kSmallMaxNf];
+  __shared__ T lcol[2 * kSmallMaxNf];
   const int s = fronts[blockIdx.x];
   const int tid = threadIdx.x;
   const int64_t f0 = M.sfirst[s];
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(NT) void k_small_fronts(FrontMeta M, const int32_t*
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
   const int nu = nf - ns;
   const double sigma = *sigma_dev;
-  double* F = smem;
+  T* F = smem;
   for (int q = tid; q < nf * nf; q += NT) F[q] = 0.0;
   __syncthreads();
   for (int64_t e = M.acptr[f0] + tid; e < M.acptr[f0 + ns]; e += NT) {
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_small_fronts(FrontMeta M, const int32_t*
   for (int64_t q = M.cptr[s]; q < M.cptr[s + 1]; q++) {
     const int c = M.clist[q];
     const int nuc = (int)(M.rptr[c + 1] - M.rptr[c] - (M.sfirst[c + 1] - M.sfirst[c]));
-    const double* Uc = U + M.uptr[c];
+    const T* Uc = U + M.uptr[c];
     const int32_t* map = M.emap + M.eptr[c];
     for (int x = tid; x < nuc * nuc; x += NT) {
       const int a = x % nuc, b = x / nuc;
@@ -443,8 +445,8 @@ __global__ __launch_bounds__(NT) void k_small_fronts(FrontMeta M, const int32_t*
     __syncthreads();
   }
   BKCounts cnt{0, 0, 0, 0, INFINITY, 0.0};
-  bk_factor_lds<NT>(F, nf, nf, ns, lp, dd, ee, lcol, cnt, sv, si);
-  double* Lp = L + M.lptr[s];
+  bk_factor_lds<NT, T>(F, nf, nf, ns, lp, dd, ee, lcol, cnt, sv, si);
+  T* Lp = L + M.lptr[s];
   for (int q = tid; q < nf * ns; q += NT) Lp[q] = F[q];
   for (int q = tid; q < ns; q += NT) {
     D[f0 + q] = dd[q];
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(NT) void k_small_fronts(FrontMeta M, const int32_t*
     tperm[f0 + q] = lp[q];
   }
   if (M.uptr[s] >= 0 && nu > 0) {
-    double* Ub = U + M.uptr[s];
+    T* Ub = U + M.uptr[s];
     for (int x = tid; x < nu * nu; x += NT) {
       const int a = x % nu, b = x / nu;
       if (a >= b) Ub[x] = F[(ns + a) + (ns + b) * nf];
@@ -464,17 +466,19 @@ __global__ __launch_bounds__(NT) void k_small_fronts(FrontMeta M, const int32_t*
 // ---------------------------------------------------------------------------
 // Large fronts: assembly of a column chunk.
 // ---------------------------------------------------------------------------
+template <typename T>
 struct FrontRef {
-  double* Lp;  // panel, ld nf
-  double* Ub;  // update block, ld nu (may be null)
+  T* Lp;  // panel, ld nf
+  T* Ub;  // update block, ld nu (may be null)
   int nf, ns, nu;
-  __device__ inline double* at(int i, int j) const {
+  __device__ inline T* at(int i, int j) const {
     return j < ns ? Lp + i + (int64_t)j * nf : Ub + (i - ns) + (int64_t)(j - ns) * nu;
   }
 };
 
-__device__ inline FrontRef front_ref(const FrontMeta& M, int s, double* L, double* U) {
-  FrontRef f;
+template <typename T>
+__device__ inline FrontRef<T> front_ref(const FrontMeta& M, int s, T* L, T* U) {
+  FrontRef<T> f;
   const int64_t f0 = M.sfirst[s];
   f.ns = (int)(M.sfirst[s + 1] - f0);
   f.nf = (int)(M.rptr[s + 1] - M.rptr[s]);
@@ -484,17 +488,17 @@ __device__ inline FrontRef front_ref(const FrontMeta& M, int s, double* L, doubl
   return f;
 }
 
-template <int NT>
+template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* tasks,
                                                    const double* __restrict__ aval,
                                                    const double* __restrict__ bval,
-                                                   Batch bt, double* L, double* U) {
+                                                   Batch bt, T* L, T* U) {
   const int64_t bidx = blockIdx.y;
   L += bidx * bt.sL; U += bidx * bt.sU;
   const double* sigma_dev = bt.sig + bidx;
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, c0 = tk.b;
-  const FrontRef f = front_ref(M, s, L, U);
+  const FrontRef<T> f = front_ref<T>(M, s, L, U);
   const int c1 = min(c0 + kAsmCols, f.nf);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
@@ -515,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* task
   for (int64_t q = M.cptr[s]; q < M.cptr[s + 1]; q++) {
     const int c = M.clist[q];
     const int nuc = (int)(M.rptr[c + 1] - M.rptr[c] - (M.sfirst[c + 1] - M.sfirst[c]));
-    const double* Uc = U + M.uptr[c];
+    const T* Uc = U + M.uptr[c];
     const int32_t* map = M.emap + M.eptr[c];
     // child columns b whose parent column map[b] lies in [c0, c1)
     int lo = 0, hi = nuc;
@@ -535,23 +539,23 @@ __global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* task
 // ---------------------------------------------------------------------------
 // Large fronts: Bunch-Kaufman inside pivot tile t (kNB columns), in LDS.
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* fronts, int t,
-                                                    Batch bt, double* L, double* D, double* E,
-                                                    int32_t* tperm, double* tinv, FactStats* st) {
+                                                    Batch bt, T* L, double* D, double* E,
+                                                    int32_t* tperm, T* tinv, FactStats* st) {
   {
     const int64_t bidx = blockIdx.y;
     L += bidx * bt.sL; D += bidx * bt.sN; E += bidx * bt.sN; tperm += bidx * bt.sN;
     tinv += bidx * bt.sT; st += bidx;
   }
   constexpr int LD = kNB + 1;   // padded: row walks across lanes hit distinct LDS banks
-  __shared__ double T[kNB * LD];
-  __shared__ double Linv[kNB * LD];
+  __shared__ T Tl[kNB * LD];
+  __shared__ T Linv[kNB * LD];
   __shared__ double sv[(NT + 63) / 64];
   __shared__ int si[(NT + 63) / 64];
   __shared__ int lp[kNB];
-  __shared__ double dd[kNB], ee[kNB];
-  __shared__ double lcol[2 * kNB];
+  __shared__ T dd[kNB], ee[kNB];
+  __shared__ T lcol[2 * kNB];
   __shared__ int dec[2];
   const int s = fronts[blockIdx.x];
   const int tid = threadIdx.x;
@@ -560,10 +564,10 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
   const int k0 = t * kNB;
   const int kb = min(kNB, ns - k0);
-  double* Lp = L + M.lptr[s];
+  T* Lp = L + M.lptr[s];
   constexpr int U = 16;   // independent global accesses in flight per thread
   for (int x0 = 0; x0 < kb * kb; x0 += NT * U) {
-    double v[U];
+    T v[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = x0 + u * NT + tid;
@@ -573,19 +577,19 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = x0 + u * NT + tid;
-      if (x < kb * kb) T[(x % kb) + (x / kb) * LD] = v[u];
+      if (x < kb * kb) Tl[(x % kb) + (x / kb) * LD] = v[u];
     }
   }
   __syncthreads();
   BKCounts cnt{0, 0, 0, 0, INFINITY, 0.0};
-  bk_tile_lds(T, LD, kb, lp, dd, ee, lcol, cnt, dec);
+  bk_tile_lds<T>(Tl, LD, kb, lp, dd, ee, lcol, cnt, dec);
   __syncthreads();
   for (int x0 = 0; x0 < kb * kb; x0 += NT * U) {
-    double v[U];
+    T v[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = x0 + u * NT + tid;
-      v[u] = x < kb * kb ? T[(x % kb) + (x / kb) * LD] : 0.0;
+      v[u] = x < kb * kb ? Tl[(x % kb) + (x / kb) * LD] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -611,14 +615,14 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
     const int w = p + 1, cnt2 = (kb - 1 - p) * w;
     for (int x = tid; x < cnt2; x += NT) {
       const int r = p + 1 + x / w, c = x % w;
-      Linv[r + c * LD] -= T[r + p * LD] * Linv[p + c * LD];
+      Linv[r + c * LD] -= Tl[r + p * LD] * Linv[p + c * LD];
     }
     __syncthreads();
   }
   __syncthreads();
-  double* Ti = tinv + M.tptr[s];
+  T* Ti = tinv + M.tptr[s];
   for (int x0 = 0; x0 < kNB * kNB; x0 += NT * U) {
-    double v[U];
+    T v[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = x0 + u * NT + tid;
@@ -631,6 +635,29 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
 }
 
 typedef double double4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 matrix-core step per element type.  Inputs: lane l supplies
+// A(m = l % 16, k = l / 16) and B(k = l / 16, n = l % 16).  Output register r of
+// lane l holds column n = l % 16 and row mrow(r, l) -- the FP64 and FP32
+// instructions differ here (pinned by the probe tests).
+template <typename T> struct MF;
+template <> struct MF<double> {
+  typedef double4v acc;
+  __device__ static inline acc zero() { return (double4v){0.0, 0.0, 0.0, 0.0}; }
+  __device__ static inline acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int mrow(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+template <> struct MF<float> {
+  typedef float4v acc;
+  __device__ static inline acc zero() { return (float4v){0.f, 0.f, 0.f, 0.f}; }
+  __device__ static inline acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int mrow(int r, int lane) { return 4 * (lane >> 4) + r; }
+};
 
 // ---------------------------------------------------------------------------
 // Large fronts: rows below pivot tile t, 64 rows per workgroup.
@@ -638,22 +665,22 @@ typedef double double4v __attribute__((ext_vector_type(4)));
 //   L21 = W D^{-1}       (1x1 / 2x2 blocks)
 // The panel rows receive L21, the workspace receives W (= L21 D).
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* tasks, int t,
-                                                   Batch bt, double* L, double* W,
+                                                   Batch bt, T* L, T* W,
                                                    const double* __restrict__ D,
                                                    const double* __restrict__ E,
                                                    const int32_t* __restrict__ tperm,
-                                                   const double* __restrict__ tinv,
+                                                   const T* __restrict__ tinv,
                                                    FactStats* st) {
   {
     const int64_t bidx = blockIdx.y;
     L += bidx * bt.sL; W += bidx * bt.sW; D += bidx * bt.sN; E += bidx * bt.sN;
     tperm += bidx * bt.sN; tinv += bidx * bt.sT; st += bidx;
   }
-  __shared__ double As[kTile * kNB];   // S' rows x k, ld kTile; reused for W
-  __shared__ double Bs[kNB * kNB];     // Linv(q, p) at q + p*kNB
-  __shared__ double dd[kNB], ee[kNB];
+  __shared__ T As[kTile * kNB];   // S' rows x k, ld kTile; reused for W
+  __shared__ T Bs[kNB * kNB];     // Linv(q, p) at q + p*kNB
+  __shared__ T dd[kNB], ee[kNB];
   __shared__ int pp[kNB];
   __shared__ double sv[NT / 64];
   const Int2 tk = tasks[blockIdx.x];
@@ -664,9 +691,9 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
   const int k0 = t * kNB;
   const int kb = min(kNB, ns - k0);
-  double* Lp = L + M.lptr[s];
-  double* Wp = W + M.wptr[s];
-  const double* Ti = tinv + M.tptr[s];
+  T* Lp = L + M.lptr[s];
+  T* Wp = W + M.wptr[s];
+  const T* Ti = tinv + M.tptr[s];
   for (int q = tid; q < kNB; q += NT) {
     dd[q] = q < kb ? D[f0 + k0 + q] : 1.0;
     ee[q] = q < kb ? E[f0 + k0 + q] : 0.0;
@@ -676,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
   __syncthreads();   // pp[] visible
   {
     constexpr int U = kTile * kNB / NT;   // 16 loads of each operand per thread, all in flight
-    double va[U], vb[U];
+    T va[U], vb[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = u * NT + tid;
@@ -693,14 +720,14 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  double4v acc[2][2];
+  typename MF<T>::acc acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++) acc[a][b] = (double4v){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; b++) acc[a][b] = MF<T>::zero();
   const int m = lane & 15, kk = lane >> 4;
   for (int q0 = 0; q0 < kNB; q0 += 4) {
-    double av[2], bv[2];
+    T av[2], bv[2];
 #pragma unroll
     for (int a = 0; a < 2; a++) av[a] = As[(wr + a * 16 + m) + (q0 + kk) * kTile];
 #pragma unroll
@@ -709,7 +736,7 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
     for (int a = 0; a < 2; a++)
 #pragma unroll
       for (int b = 0; b < 2; b++)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = MF<T>::step(av[a], bv[b], acc[a][b]);
   }
   __syncthreads();   // everyone is done reading As
 #pragma unroll
@@ -718,26 +745,26 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
     for (int b = 0; b < 2; b++)
 #pragma unroll
       for (int r = 0; r < 4; r++)
-        As[(wr + a * 16 + 4 * r + (lane >> 4)) + (wc + b * 16 + (lane & 15)) * kTile] = acc[a][b][r];
+        As[(wr + a * 16 + MF<T>::mrow(r, lane)) + (wc + b * 16 + (lane & 15)) * kTile] = acc[a][b][r];
   __syncthreads();
   double maxl = 0.0;
   for (int x = tid; x < kTile * kNB; x += NT) {
     const int r = x % kTile, q = x / kTile;
     if (r >= nr || q >= kb) continue;
-    const double wq = As[r + q * kTile];
-    double l;
+    const T wq = As[r + q * kTile];
+    T l;
     if (q + 1 < kb && ee[q] != 0.0) {            // first row of a 2x2 block
-      const double a = dd[q], b = ee[q], c = dd[q + 1], det = a * c - b * b;
+      const T a = dd[q], b = ee[q], c = dd[q + 1], det = a * c - b * b;
       l = (c * wq - b * As[r + (q + 1) * kTile]) / det;
     } else if (q > 0 && ee[q - 1] != 0.0) {      // second row of a 2x2 block
-      const double a = dd[q - 1], b = ee[q - 1], c = dd[q], det = a * c - b * b;
+      const T a = dd[q - 1], b = ee[q - 1], c = dd[q], det = a * c - b * b;
       l = (a * wq - b * As[r + (q - 1) * kTile]) / det;
     } else {
       l = dd[q] != 0.0 ? wq / dd[q] : 0.0;
     }
     Lp[(r0 + r) + (int64_t)(k0 + q) * nf] = l;
     Wp[(r0 + r) + (int64_t)q * nf] = wq;
-    maxl = fmax(maxl, fabs(l));
+    maxl = fmax(maxl, fabs((double)l));
   }
   maxl = block_max<NT>(maxl, sv);
   if (tid == 0) atomicMax(&st->max_l_bits, dbits(maxl));
@@ -753,23 +780,23 @@ __device__ inline void chunk_range(int c, int r0, int ns, int nf, int nc1, int& 
   else { b = ns + (c - nc1) * kTile; e = min(b + kTile, nf); }
 }
 
-template <int NT>
+template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts,
                                               const int32_t* tile_prefix, int nfronts, int t,
-                                              Batch bt, double* L, double* U, const double* W) {
+                                              Batch bt, T* L, T* U, const T* W) {
   {
     const int64_t bidx = blockIdx.y;
     L += bidx * bt.sL; U += bidx * bt.sU; W += bidx * bt.sW;
   }
-  __shared__ double As[kTile * kNB];  // W rows (i) x k, ld kTile
-  __shared__ double Bs[kTile * kNB];  // L rows (j) x k, ld kTile
+  __shared__ T As[kTile * kNB];  // W rows (i) x k, ld kTile
+  __shared__ T Bs[kTile * kNB];  // L rows (j) x k, ld kTile
   // locate the front of this tile
   const int g = blockIdx.x;
   int lo = 0, hi = nfronts - 1;
   while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (tile_prefix[mid] <= g) lo = mid; else hi = mid - 1; }
   const int s = fronts[lo];
   const int tl = g - tile_prefix[lo];
-  const FrontRef f = front_ref(M, s, L, U);
+  const FrontRef<T> f = front_ref<T>(M, s, L, U);
   const int k0 = t * kNB;
   const int kb = min(kNB, f.ns - k0);
   const int r0 = k0 + kb;
@@ -782,36 +809,36 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
   int ib, ie, jb, je;
   chunk_range(bi, r0, f.ns, f.nf, nc1, ib, ie);
   chunk_range(bj, r0, f.ns, f.nf, nc1, jb, je);
-  const double* Lp = f.Lp;
-  const double* Wp = W + M.wptr[s];
+  const T* Lp = f.Lp;
+  const T* Wp = W + M.wptr[s];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   // wave's 32x32 sub-tile: rows (i) wr.., columns (j) wc..
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   // C tile base: chunks never straddle ns, so the tile lies in the panel or in the update block
-  double* Cb;
+  T* Cb;
   int64_t ldc;
   if (jb < f.ns) { Cb = f.Lp + ib + (int64_t)jb * f.nf; ldc = f.nf; }
   else { Cb = f.Ub + (ib - f.ns) + (int64_t)(jb - f.ns) * f.nu; ldc = f.nu; }
   // Output layout with A = L rows (j) and B = W rows (i): lane l holds i = l % 16 of
   // its block and j = 4 r + l / 16 for register r -> 16 consecutive rows per column.
-  const int il = lane & 15, jl = lane >> 4;
+  const int il = lane & 15;
   const bool diag = (bi == bj);
   // prefetch the C entries this thread will update (overlaps the operand staging)
-  double cv[2][2][4];
+  T cv[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
     for (int b = 0; b < 2; b++)
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int i = wr + a * 16 + il, j = wc + b * 16 + 4 * r + jl;
+        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
         const bool ok = (ib + i < ie) && (jb + j < je) && (!diag || i >= j);
         cv[a][b][r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
       }
   {
     constexpr int U = kTile * kNB / NT;   // 16 loads of each operand per thread, all in flight
-    double va[U], vb[U];
+    T va[U], vb[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = u * NT + tid;
@@ -827,14 +854,14 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
     }
   }
   __syncthreads();
-  double4v acc[2][2];
+  typename MF<T>::acc acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++) acc[a][b] = (double4v){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; b++) acc[a][b] = MF<T>::zero();
   const int m = lane & 15, kk = lane >> 4;
   for (int q0 = 0; q0 < kNB; q0 += 4) {
-    double wv[2], lv[2];
+    T wv[2], lv[2];
 #pragma unroll
     for (int a = 0; a < 2; a++) wv[a] = As[(wr + a * 16 + m) + (q0 + kk) * kTile];
 #pragma unroll
@@ -844,7 +871,7 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
     for (int a = 0; a < 2; a++)
 #pragma unroll
       for (int b = 0; b < 2; b++)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[b], wv[a], acc[a][b], 0, 0, 0);
+        acc[a][b] = MF<T>::step(lv[b], wv[a], acc[a][b]);
   }
   // write back: C(i, j) -= acc for i >= j inside the chunk bounds
 #pragma unroll
@@ -853,7 +880,7 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
     for (int b = 0; b < 2; b++)
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int i = wr + a * 16 + il, j = wc + b * 16 + 4 * r + jl;
+        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
         const bool ok = (ib + i < ie) && (jb + j < je) && (!diag || i >= j);
         if (ok) Cb[i + (int64_t)j * ldc] = cv[a][b][r] - acc[a][b][r];
       }
@@ -865,6 +892,14 @@ __global__ void k_set_scalar(double* p, double v) {
 
 __global__ void k_set_scalars(double* p, int n, SigmaPack pk) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = pk.v[threadIdx.x];
+}
+
+// Raw probe of the FP32 instruction (same convention as the FP64 probe below).
+__global__ void k_mfma_probe_f32(const float* A, const float* B, float* Dout) {
+  const int lane = threadIdx.x;
+  float4v c = {0.f, 0.f, 0.f, 0.f};
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(A[lane], B[lane], c, 0, 0, 0);
+  for (int r = 0; r < 4; r++) Dout[4 * lane + r] = c[r];
 }
 
 // Raw probe: lane l feeds a[l] and b[l]; c[4 l + r] receives result register r.
@@ -884,55 +919,76 @@ void launch_fill_stats(FactStats* st, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_stats, dim3(nb), dim3(64), 0, s, st);
 }
 
+template <typename T>
 void launch_small_fronts(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t max_nf,
                          const double* aval, const double* bval, const Batch& bt, int nb,
-                         double* L, double* U, double* D, double* E, int32_t* tperm,
+                         T* L, T* U, double* D, double* E, int32_t* tperm,
                          FactStats* st, hipStream_t s) {
   if (count <= 0) return;
-  const size_t lds = (size_t)max_nf * max_nf * sizeof(double);
+  const size_t lds = (size_t)max_nf * max_nf * sizeof(T);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_small_fronts<256>,
+    (void)hipFuncSetAttribute((const void*)k_small_fronts<256, T>,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kSmallMaxNf * kSmallMaxNf * (int)sizeof(double));
+                              kSmallMaxNf * kSmallMaxNf * (int)sizeof(T));
     attr = true;
   }
-  hipLaunchKernelGGL(k_small_fronts<256>, dim3(count, nb), dim3(256), lds, s, M, fronts, aval, bval,
-                     bt, L, U, D, E, tperm, st);
+  hipLaunchKernelGGL((k_small_fronts<256, T>), dim3(count, nb), dim3(256), lds, s, M, fronts, aval,
+                     bval, bt, L, U, D, E, tperm, st);
 }
 
+template <typename T>
 void launch_front_init(const FrontMeta& M, const Int2* tasks, int32_t count, const double* aval,
-                       const double* bval, const Batch& bt, int nb, double* L, double* U,
-                       hipStream_t s) {
+                       const double* bval, const Batch& bt, int nb, T* L, T* U, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_front_init<256>, dim3(count, nb), dim3(256), 0, s, M, tasks, aval, bval, bt,
-                     L, U);
+  hipLaunchKernelGGL((k_front_init<256, T>), dim3(count, nb), dim3(256), 0, s, M, tasks, aval, bval,
+                     bt, L, U);
 }
 
+template <typename T>
 void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t t,
-                        const Batch& bt, int nb, double* L, double* D, double* E, int32_t* tperm,
-                        double* tinv, FactStats* st, hipStream_t s) {
+                        const Batch& bt, int nb, T* L, double* D, double* E, int32_t* tperm,
+                        T* tinv, FactStats* st, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_tile_factor<256>, dim3(count, nb), dim3(256), 0, s, M, fronts, t, bt, L, D,
-                     E, tperm, tinv, st);
+  hipLaunchKernelGGL((k_tile_factor<256, T>), dim3(count, nb), dim3(256), 0, s, M, fronts, t, bt, L,
+                     D, E, tperm, tinv, st);
 }
 
+template <typename T>
 void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t,
-                       const Batch& bt, int nb, double* L, double* W, const double* D,
-                       const double* E, const int32_t* tperm, const double* tinv, FactStats* st,
-                       hipStream_t s) {
+                       const Batch& bt, int nb, T* L, T* W, const double* D, const double* E,
+                       const int32_t* tperm, const T* tinv, FactStats* st, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_panel_trsm<256>, dim3(count, nb), dim3(256), 0, s, M, tasks, t, bt, L, W, D,
-                     E, tperm, tinv, st);
+  hipLaunchKernelGGL((k_panel_trsm<256, T>), dim3(count, nb), dim3(256), 0, s, M, tasks, t, bt, L, W,
+                     D, E, tperm, tinv, st);
 }
 
+template <typename T>
 void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
-                  int32_t nfronts, int32_t ntiles, int32_t t, const Batch& bt, int nb, double* L,
-                  double* U, const double* W, hipStream_t s) {
+                  int32_t nfronts, int32_t ntiles, int32_t t, const Batch& bt, int nb, T* L, T* U,
+                  const T* W, hipStream_t s) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_schur<256>, dim3(ntiles, nb), dim3(256), 0, s, M, fronts, tile_prefix,
+  hipLaunchKernelGGL((k_schur<256, T>), dim3(ntiles, nb), dim3(256), 0, s, M, fronts, tile_prefix,
                      nfronts, t, bt, L, U, W);
 }
+
+#define KTH_INSTANTIATE_FACTOR(T)                                                                   \
+  template void launch_small_fronts<T>(const FrontMeta&, const int32_t*, int32_t, int32_t,         \
+                                       const double*, const double*, const Batch&, int, T*, T*,     \
+                                       double*, double*, int32_t*, FactStats*, hipStream_t);        \
+  template void launch_front_init<T>(const FrontMeta&, const Int2*, int32_t, const double*,        \
+                                     const double*, const Batch&, int, T*, T*, hipStream_t);        \
+  template void launch_tile_factor<T>(const FrontMeta&, const int32_t*, int32_t, int32_t,          \
+                                      const Batch&, int, T*, double*, double*, int32_t*, T*,        \
+                                      FactStats*, hipStream_t);                                     \
+  template void launch_panel_trsm<T>(const FrontMeta&, const Int2*, int32_t, int32_t, const Batch&, \
+                                     int, T*, T*, const double*, const double*, const int32_t*,     \
+                                     const T*, FactStats*, hipStream_t);                            \
+  template void launch_schur<T>(const FrontMeta&, const int32_t*, const int32_t*, int32_t, int32_t, \
+                                int32_t, const Batch&, int, T*, T*, const T*, hipStream_t);
+KTH_INSTANTIATE_FACTOR(double)
+KTH_INSTANTIATE_FACTOR(float)
+#undef KTH_INSTANTIATE_FACTOR
 
 void launch_set_scalar(double* p, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, p, v);
@@ -943,6 +999,10 @@ void launch_set_scalars(double* p, int n, const double* v8, hipStream_t s) {
   SigmaPack pk;
   for (int i = 0; i < n && i < kMaxBatch; i++) pk.v[i] = v8[i];
   hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, p, n, pk);
+}
+
+void launch_mfma_probe_f32(const float* A, const float* B, float* D, hipStream_t s) {
+  hipLaunchKernelGGL(k_mfma_probe_f32, dim3(1), dim3(64), 0, s, A, B, D);
 }
 
 void launch_mfma_probe(const double* A, const double* B, double* D, hipStream_t s) {

@@ -162,3 +162,30 @@ def test_hellmann_feynman_backward(K, ctx):
         fd = (vals[0] - vals[1]) / (2 * h)
         an = ga[q] + ga[q2]
         assert abs(fd - an) <= 1e-7 + 1e-4 * abs(an), (i, j, fd, an)
+
+
+def test_handle_release_order(K):
+    # a kept factor stays usable after its pencil and context handles are destroyed
+    p = pg.tb_supercell((2, 2, 2), seed=5)
+    note("handle release order")
+    c2 = K.Context(0)
+    P = K.Pencil.from_pencilgen(c2, p)
+    F = P.factor(-3.0)
+    b = np.random.default_rng(2).normal(size=p.n)
+    x_before = F.solve(b)
+    c2.close()
+    P.close()
+    x_after = F.solve(b)
+    assert np.array_equal(x_before, x_after)
+    F.close()
+
+
+def test_option_validation(K, ctx):
+    p = pg.tb_supercell((2, 2, 2), seed=6)
+    note("option validation")
+    P = K.Pencil.from_pencilgen(ctx, p)
+    for bad in (dict(multisection=0), dict(multisection=65), dict(m_max=0), dict(ir_tol=-1.0),
+                dict(si_precision=7), dict(max_lanczos=0), dict(tau_res=0.0)):
+        with pytest.raises(K.KthError) as e:
+            P.eig(p.n // 2, **bad)
+        assert e.value.status == K.KTH_EINVAL, bad
