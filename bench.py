@@ -62,6 +62,120 @@ def cpu_baseline(pencil, sigma: float, n_factorizations: int, sample_flops: floa
     }
 
 
+KERNEL_SOURCES = ("paper_1710_05134_amd/csrc/factor.hip", "paper_1710_05134_amd/csrc/device.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_schur_n524k_traffic.md")
+PMC_SIGMA = -3.0
+COPY_DOUBLES = 2 ** 27          # calibration copy: 1 GiB read + 1 GiB written
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def schur_traffic():
+    """HBM bytes per k_schur launch from the committed counter summary, or None if
+    it is missing or was taken on other kernel sources."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip("` ")] = v.strip().strip("`")
+        if kv.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["k_schur_hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def pmc_sample():
+    """One FP64 factorization of the bench pencil at sigma = PMC_SIGMA, then a plain
+    1 GiB device copy that calibrates FETCH_SIZE / WRITE_SIZE (run under rocprofv3 --pmc)."""
+    import torch
+    import pencilgen as pg
+    import paper_1710_05134_amd as K
+    torch.cuda.init()
+    p = pg.workload("n524k")
+    ctx = K.Context(0)
+    P = K.Pencil.from_pencilgen(ctx, p)
+    nu = P.nu(PMC_SIGMA)
+    log(f"factorization at sigma={PMC_SIGMA}: nu={nu}")
+    x = torch.empty(COPY_DOUBLES, dtype=torch.float64, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_sample": "n524k", "sigma": PMC_SIGMA, "nu": nu,
+                      "copy_bytes": 8 * COPY_DOUBLES}), flush=True)
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize(stats_csv, fetch_csv, write_csv, command, pmc_command):
+    """Markdown summary of a rocprofv3 kernel-stats CSV and, if given, of the
+    FETCH_SIZE / WRITE_SIZE counter CSVs of a --pmc-sample run."""
+    out = []
+    if stats_csv:
+        rows = _read_csv(stats_csv)
+        out += ["# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+                "| kernel | calls | avg µs | total ms | % |", "|---|---|---|---|---|"]
+        for r in rows[:15]:
+            name = r["Name"].replace("kth::(anonymous namespace)::", "")
+            name = name.split("(")[0] if "kth" in r["Name"] else name[:60]
+            out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                       f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.1f} |")
+        out.append("")
+    if fetch_csv and write_csv:
+        def per_kernel(path):
+            acc = {}   # name -> [sum of bytes, dispatches, largest single dispatch]
+            for r in _read_csv(path):
+                nm = r["Kernel_Name"]
+                v = float(r["Counter_Value"]) * 1024.0
+                a = acc.setdefault(nm, [0.0, 0, 0.0])
+                a[0] += v
+                a[1] += 1
+                a[2] = max(a[2], v)
+            return acc
+        fe, wr = per_kernel(fetch_csv), per_kernel(write_csv)
+        # the calibration copy is the largest single dispatch of a copy kernel
+        copy = max((nm for nm in fe if "copy" in nm.lower()), key=lambda nm: fe[nm][2])
+        f_fac = (8 * COPY_DOUBLES) / fe[copy][2]
+        w_fac = (8 * COPY_DOUBLES) / wr[copy][2]
+        out += ["# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)", "",
+                f"Command (once per counter): `{pmc_command}`", "",
+                f"Calibration: the 1 GiB device copy (`{copy[:60]}`) read FETCH_SIZE "
+                f"{fe[copy][2] / 2**30:.3f} GiB and WRITE_SIZE {wr[copy][2] / 2**30:.3f} GiB; "
+                f"scale factors {f_fac:.3f} (fetch), {w_fac:.3f} (write).", "",
+                "| kernel | dispatches | read GB / dispatch | written GB / dispatch | total GB |",
+                "|---|---|---|---|---|"]
+        keys = sorted((nm for nm in fe if nm.startswith("void kth")), key=lambda nm: -fe[nm][0])
+        for nm in keys:
+            rf = fe[nm][0] * f_fac / fe[nm][1]
+            rw = wr.get(nm, [0.0, 1])[0] * w_fac / max(wr.get(nm, [0.0, 1])[1], 1)
+            short = nm.replace("void kth::(anonymous namespace)::", "").split("(")[0]
+            out.append(f"| `{short}` | {fe[nm][1]} | {rf / 1e9:.4f} | {rw / 1e9:.4f} | "
+                       f"{(rf + rw) * fe[nm][1] / 1e9:.2f} |")
+        sch = [nm for nm in keys if "k_schur<256, double>" in nm or "k_schur<256>" in nm]
+        if sch:
+            nm = sch[0]
+            per = fe[nm][0] * f_fac / fe[nm][1] + wr[nm][0] * w_fac / wr[nm][1]
+            out += ["", f"- k_schur_hbm_bytes_per_launch: {per:.6e}",
+                    f"- k_schur_launches: {fe[nm][1]}",
+                    f"- kernel_source_sha256: `{kernel_source_hash()}`"]
+        out.append("")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,11 +185,25 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-flops", type=float, default=1e10)
     ap.add_argument("--profile-reps", type=int, default=3)
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="one factorization + a 1 GiB calibration copy, for rocprofv3 --pmc")
+    ap.add_argument("--summarize", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="print the markdown summary of rocprofv3 CSVs ('-' to skip one)")
+    ap.add_argument("--summary-command", default="")
+    ap.add_argument("--summary-pmc-command", default="")
     args = ap.parse_args()
+    if args.summarize:
+        st, fe, wr = (None if a == "-" else a for a in args.summarize)
+        summarize(st, fe, wr, args.summary_command, args.summary_pmc_command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.pmc_sample:
+        pmc_sample()
+        return
 
     import torch
     import pencilgen as pg
@@ -117,6 +245,9 @@ def main():
     sch_s = statistics.median(pr["schur"]["seconds"] for pr in profs)
     sch = profs[0]["schur"]
     per_launch_flops = sch["flops"] / max(sch["launches"], 1)
+    # algorithmic bytes: each updated lower-triangle entry read and written once (16 B per
+    # 128 flops of a rank-64 update); the two 64-column panels are not counted
+    sch_bytes = sch["flops"] / 8.0
     avg_launch_s = sch_s / max(sch["launches"], 1)
     achieved = per_launch_flops / avg_launch_s / 1e12
     log(f"factorization {tot * 1e3:.1f} ms = {ldlt_gflops:.0f} GFLOP/s; schur {sch_s * 1e3:.1f} ms "
@@ -159,7 +290,9 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": schur_traffic(),
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": sch_bytes / max(sch["launches"], 1),
             "launches": sch["launches"],
             "flops_per_launch": per_launch_flops,
             "avg_launch_us": avg_launch_s * 1e6,
