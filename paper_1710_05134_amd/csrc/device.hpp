@@ -43,6 +43,8 @@ constexpr int kAsmCols = 16;
 constexpr int kTrsmRows = 64;
 // Rows per gather task of the large-front solve.
 constexpr int kSolveChunk = 256;
+// rows below a pivot tile per workgroup of a large-front solve step
+constexpr int kSolveRows = 256;
 // Schur-update output tile.
 constexpr int kTile = 64;
 

@@ -145,9 +145,17 @@ static void build_schedule(Pencil& P) {
       SolveStep ss;
       ss.t = sp.t;
       ss.nfronts = sp.nfronts;
-      ss.task_off = sp.trsm_off;
-      ss.task_cnt = sp.trsm_cnt;
-      ss.prefix_off = sp.trsm_prefix_off;
+      align2();
+      ss.task_off = (int32_t)sched.size();
+      for (int32_t q = 0; q < sp.nfronts; q++) {
+        const int32_t s = sched[lp.large_off + q];
+        const int64_t ns = S.ns(s), nf = S.nf(s);
+        const int64_t rb = std::min<int64_t>(sp.t * (int64_t)kNB + kNB, ns);
+        if (rb >= nf) { sched.push_back(s); sched.push_back((int32_t)nf); }
+        for (int64_t r = rb; r < nf; r += kSolveRows) { sched.push_back(s); sched.push_back((int32_t)r); }
+      }
+      ss.task_cnt = (int32_t)((sched.size() - ss.task_off) / 2);
+      P.splan.partial_size = std::max<int64_t>(P.splan.partial_size, (int64_t)ss.task_cnt * kNB);
       sl.steps.push_back(ss);
     }
   }
@@ -433,15 +441,17 @@ void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x) {
     F.ye.alloc(c, (size_t)P.n);
     F.R.alloc(c, P.S.rows.size());
     F.partial.alloc(c, (size_t)P.splan.partial_size);
+    F.counter.alloc(c, (size_t)P.S.nsup);
+    KTH_HIP(hipMemsetAsync(F.counter.get(), 0, sizeof(int32_t) * P.S.nsup, c->stream));
   }
   if (F.prec == KTH_FP64)
     solve_enqueue<double>(P.splan, P.meta, F.L.get(), F.D.get(), F.E.get(), F.tperm.get(),
                           P.d_perm.get(), P.n, b, x, F.xe.get(), F.ye.get(), F.R.get(),
-                          F.partial.get(), c->stream);
+                          F.partial.get(), F.counter.get(), c->stream);
   else
     solve_enqueue<float>(P.splan, P.meta, reinterpret_cast<const float*>(F.L.get()), F.D.get(),
                          F.E.get(), F.tperm.get(), P.d_perm.get(), P.n, b, x, F.xe.get(),
-                         F.ye.get(), F.R.get(), F.partial.get(), c->stream);
+                         F.ye.get(), F.R.get(), F.partial.get(), F.counter.get(), c->stream);
 }
 
 }  // namespace kth

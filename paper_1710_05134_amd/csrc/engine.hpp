@@ -137,6 +137,7 @@ struct NumFactor {
   bool have_stats = false;
   // solve scratch
   DBuf<double> xe, ye, R, partial;
+  DBuf<int32_t> counter;      // per-supernode completion counters of the backward steps
   // refinement scratch (FP32 factors): residual, Krylov basis, dot partials, small results
   DBuf<double> ir_r, ir_V, ir_part, ir_out;
 };

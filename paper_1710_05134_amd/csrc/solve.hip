@@ -174,135 +174,134 @@ __global__ __launch_bounds__(NT) void k_lfwd_init(FrontMeta M, const Int2* tasks
   }
 }
 
-// one wavefront per front: z = P_t r_t, L_tt z = P_t r_t, written back in place
-template <typename T>
-__global__ __launch_bounds__(64) void k_lfwd_tile(FrontMeta M, const int32_t* fronts, int t,
-                                                  const T* L, const int32_t* __restrict__ tperm,
-                                                  double* R) {
-  const int s = fronts[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int64_t f0 = M.sfirst[s];
-  const int ns = (int)(M.sfirst[s + 1] - f0);
-  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
-  const int k0 = t * kNB, kb = min(kNB, ns - k0);
-  const T* Lp = L + M.lptr[s];
-  double* Rs = R + M.rptr[s];
-  double z = lane < kb ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
-  for (int p = 0; p < kb; p++) {
-    const double zp = __shfl(z, p);
-    if (lane > p && lane < kb) z -= (double)Lp[(k0 + lane) + (int64_t)(k0 + p) * nf] * zp;
+// y = D^{-1} z for pivot q of a tile (2x2 blocks never straddle a tile edge);
+// z: the tile's values, k = f0 + k0 + q
+__device__ inline double apply_dinv(const double* __restrict__ D, const double* __restrict__ E,
+                                    const double* z, int64_t k, int q, int kb) {
+  if (q + 1 < kb && E[k] != 0.0) {
+    const double a = D[k], b = E[k], c = D[k + 1], det = a * c - b * b;
+    return (c * z[q] - b * z[q + 1]) / det;
   }
-  if (lane < kb) Rs[k0 + lane] = z;
+  if (q > 0 && E[k - 1] != 0.0) {
+    const double a = D[k - 1], b = E[k - 1], c = D[k], det = a * c - b * b;
+    return (a * z[q] - b * z[q - 1]) / det;
+  }
+  return D[k] != 0.0 ? z[q] / D[k] : 0.0;
 }
 
-// rows [r0, r0 + kTrsmRows) below tile t: R_i -= sum_q L(i, k0+q) z_q
+// Forward tile step t of the large fronts of a level, one launch: every
+// workgroup solves L_tt z = P_t r_t itself (the 64x64 tile held in registers,
+// row = lane) and subtracts L(i, tile) z from its kSolveRows rows below the tile;
+// the workgroup of a front's first row chunk also writes y = D^{-1} z.  A front
+// without rows below the tile has one task with an empty row range.
 template <typename T>
-__global__ __launch_bounds__(64) void k_lfwd_gemv(FrontMeta M, const Int2* tasks, int t,
-                                                  const T* L, double* R) {
+__global__ __launch_bounds__(NT) void k_lfwd_step(FrontMeta M, const Int2* tasks, int t,
+                                                  const T* L, const double* __restrict__ D,
+                                                  const double* __restrict__ E,
+                                                  const int32_t* __restrict__ tperm, double* R,
+                                                  double* ye) {
   __shared__ double z[kNB];
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, r0 = tk.b;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
   const int k0 = t * kNB, kb = min(kNB, ns - k0);
   const T* Lp = L + M.lptr[s];
   double* Rs = R + M.rptr[s];
-  z[lane] = lane < kb ? Rs[k0 + lane] : 0.0;
+  if (tid < 64) {
+    double Lr[kNB];
+#pragma unroll
+    for (int p = 0; p < kNB; p++)
+      Lr[p] = (lane < kb && p < kb) ? (double)Lp[(k0 + lane) + (int64_t)(k0 + p) * nf] : 0.0;
+    double zl = lane < kb ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
+#pragma unroll
+    for (int p = 0; p < kNB; p++) {
+      const double zp = __shfl(zl, p);
+      if (lane > p) zl -= Lr[p] * zp;   // Lr[p] = 0 beyond the tile
+    }
+    z[lane] = zl;
+  }
   __syncthreads();
-  const int i = r0 + lane;
-  if (i < nf) {
+  const int i = r0 + tid;
+  if (tid < kSolveRows && i < nf) {
     double acc = 0.0;
-    for (int q = 0; q < kb; q++) acc += (double)Lp[i + (int64_t)(k0 + q) * nf] * z[q];
+    for (int q = 0; q < kb; q++) acc = fma((double)Lp[i + (int64_t)(k0 + q) * nf], z[q], acc);
     Rs[i] -= acc;
   }
+  if (r0 == k0 + kb && tid < kb) ye[f0 + k0 + tid] = apply_dinv(D, E, z, f0 + k0 + tid, tid, kb);
 }
 
-// y = D^{-1} z for the fully-summed rows of large fronts
-__global__ __launch_bounds__(NT) void k_ldiag(FrontMeta M, const int32_t* fronts,
-                                              const double* __restrict__ D,
-                                              const double* __restrict__ E,
-                                              const double* __restrict__ R, double* ye) {
-  const int s = fronts[blockIdx.x];
-  const int64_t f0 = M.sfirst[s];
-  const int ns = (int)(M.sfirst[s + 1] - f0);
-  const double* Rs = R + M.rptr[s];
-  for (int q = threadIdx.x; q < ns; q += NT) {
-    const int64_t k = f0 + q;
-    double y;
-    if (q + 1 < ns && E[k] != 0.0) {
-      const double a = D[k], b = E[k], c = D[k + 1], det = a * c - b * b;
-      y = (c * Rs[q] - b * Rs[q + 1]) / det;
-    } else if (q > 0 && E[k - 1] != 0.0 && (q % kNB) != 0) {
-      const double a = D[k - 1], b = E[k - 1], c = D[k], det = a * c - b * b;
-      y = (a * Rs[q] - b * Rs[q - 1]) / det;
-    } else {
-      y = D[k] != 0.0 ? Rs[q] / D[k] : 0.0;
-    }
-    ye[k] = y;
-  }
-}
-
-// backward: partial[task * kNB + q] = sum over the task's rows i of L(i, k0+q) x(rows[i])
+// Backward tile step t (tiles in reverse), one launch: every workgroup forms
+// partial[task][q] = sum over its rows i of L(i, k0+q) x(rows[i]) (lane = column,
+// four waves over the rows); the last workgroup of a front to finish (counted
+// with a device-scope atomic after a release fence, then an acquire fence) adds
+// the front's partials in task order, solves L_tt^T w = y_t - partial sum with
+// the tile in registers (column = lane) and writes x(f0 + k0 + perm[q]) = w_q;
+// it also resets the front's counter for the next step.
 template <typename T>
-__global__ __launch_bounds__(64) void k_lbwd_gemv(FrontMeta M, const Int2* tasks, int t,
-                                                  const T* L, const double* __restrict__ xe,
-                                                  double* partial) {
-  __shared__ double xv[kTrsmRows];
-  __shared__ double prod[(kTrsmRows + 1) * kNB];
+__global__ __launch_bounds__(NT) void k_lbwd_step(FrontMeta M, const Int2* tasks, int t,
+                                                  const T* L, const int32_t* __restrict__ tperm,
+                                                  const double* __restrict__ ye, double* partial,
+                                                  int32_t* counter, double* xe) {
+  __shared__ double wsum[NT / 64][kNB];
+  __shared__ double xv[kSolveRows];
+  __shared__ int last;
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, r0 = tk.b;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
   const int k0 = t * kNB, kb = min(kNB, ns - k0);
-  const int nr = min(kTrsmRows, nf - r0);
+  const int rb = k0 + kb;                      // first row below the tile
+  const int nr = max(0, min(kSolveRows, nf - r0));
   const T* Lp = L + M.lptr[s];
   const int32_t* rows = M.rows + M.rptr[s];
-  for (int r = lane; r < kTrsmRows; r += 64) xv[r] = r < nr ? xe[rows[r0 + r]] : 0.0;
+  if (tid < kSolveRows) xv[tid] = tid < nr ? xe[rows[r0 + tid]] : 0.0;
   __syncthreads();
-  // products staged so that every global load is coalesced (lanes over rows)
-  for (int q = 0; q < kb; q++)
-    for (int r = lane; r < kTrsmRows; r += 64)
-      prod[r + q * (kTrsmRows + 1)] =
-          r < nr ? (double)Lp[(r0 + r) + (int64_t)(k0 + q) * nf] * xv[r] : 0.0;
+  {
+    double acc = 0.0;
+    const int rw0 = wave * (kSolveRows / (NT / 64));
+    const int rw1 = min(rw0 + kSolveRows / (NT / 64), nr);
+    if (lane < kb)
+      for (int r = rw0; r < rw1; r++)
+        acc = fma((double)Lp[(r0 + r) + (int64_t)(k0 + lane) * nf], xv[r], acc);
+    wsum[wave][lane] = acc;
+  }
   __syncthreads();
-  double acc = 0.0;
-  if (lane < kb)
-    for (int r = 0; r < nr; r++) acc += prod[r + lane * (kTrsmRows + 1)];
-  partial[(int64_t)blockIdx.x * kNB + lane] = acc;
-}
-
-// one wavefront per front: g = y - sum of partials (task order), L_tt^T w = g,
-// x(f0 + k0 + perm[q]) = w_q
-template <typename T>
-__global__ __launch_bounds__(64) void k_lbwd_tile(FrontMeta M, const int32_t* fronts,
-                                                  const int32_t* task_prefix, int t, const T* L,
-                                                  const int32_t* __restrict__ tperm,
-                                                  const double* __restrict__ ye,
-                                                  const double* __restrict__ partial, double* xe) {
-  const int s = fronts[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int64_t f0 = M.sfirst[s];
-  const int ns = (int)(M.sfirst[s + 1] - f0);
-  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
-  const int k0 = t * kNB, kb = min(kNB, ns - k0);
-  const T* Lp = L + M.lptr[s];
+  const int ntask = nf > rb ? (nf - rb + kSolveRows - 1) / kSolveRows : 1;
+  const int first = (int)blockIdx.x - (r0 - rb) / kSolveRows;
+  if (tid < 64) {
+    double v = 0.0;
+    for (int w = 0; w < NT / 64; w++) v += wsum[w][lane];
+    partial[(int64_t)blockIdx.x * kNB + lane] = v;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(&counter[s], 1) == ntask - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (tid == 0) atomicExch(&counter[s], 0);
+  if (tid >= 64) return;
   double g = 0.0;
   if (lane < kb) {
     double acc = 0.0;
-    for (int q = task_prefix[blockIdx.x]; q < task_prefix[blockIdx.x + 1]; q++)
-      acc += partial[(int64_t)q * kNB + lane];
+    for (int q = first; q < first + ntask; q++) acc += partial[(int64_t)q * kNB + lane];
     g = ye[f0 + k0 + lane] - acc;
   }
-  for (int p = kb - 1; p >= 0; p--) {
+  double Lc[kNB];
+#pragma unroll
+  for (int p = 0; p < kNB; p++)
+    Lc[p] = (lane < kb && p < kb) ? (double)Lp[(k0 + p) + (int64_t)(k0 + lane) * nf] : 0.0;
+#pragma unroll
+  for (int p = kNB - 1; p >= 0; p--) {
     const double wp = __shfl(g, p);
-    if (lane < p) g -= (double)Lp[(k0 + p) + (int64_t)(k0 + lane) * nf] * wp;
+    if (lane < p) g -= Lc[p] * wp;   // Lc[p] = 0 beyond the tile
   }
   if (lane < kb) xe[f0 + k0 + tperm[f0 + k0 + lane]] = g;
-  (void)nf;
 }
 
 __global__ void k_gather(int64_t n, const int64_t* __restrict__ perm, const double* __restrict__ x,
@@ -330,7 +329,7 @@ template <typename T>
 void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const double* D,
                    const double* E, const int32_t* tperm, const int64_t* perm, int64_t n,
                    const double* b, double* x, double* xe, double* ye, double* R, double* partial,
-                   hipStream_t s) {
+                   int32_t* counter, hipStream_t s) {
   const int32_t* sc = P.sched;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(256), 0, s, n, perm, b, xe);
   for (const SolveLevel& lv : P.levels) {
@@ -340,14 +339,9 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
     if (lv.large_cnt == 0) continue;
     hipLaunchKernelGGL((k_lfwd_init<T>), dim3(lv.init_cnt), dim3(NT), 0, s, M,
                        reinterpret_cast<const Int2*>(sc + lv.init_off), xe, R);
-    for (const SolveStep& st : lv.steps) {
-      hipLaunchKernelGGL((k_lfwd_tile<T>), dim3(st.nfronts), dim3(64), 0, s, M, sc + lv.large_off,
-                         st.t, L, tperm, R);
-      if (st.task_cnt > 0)
-        hipLaunchKernelGGL((k_lfwd_gemv<T>), dim3(st.task_cnt), dim3(64), 0, s, M,
-                           reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, R);
-    }
-    hipLaunchKernelGGL(k_ldiag, dim3(lv.large_cnt), dim3(NT), 0, s, M, sc + lv.large_off, D, E, R, ye);
+    for (const SolveStep& st : lv.steps)
+      hipLaunchKernelGGL((k_lfwd_step<T>), dim3(st.task_cnt), dim3(NT), 0, s, M,
+                         reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, D, E, tperm, R, ye);
   }
   for (size_t l = P.levels.size(); l-- > 0;) {
     const SolveLevel& lv = P.levels[l];
@@ -356,11 +350,9 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
                          L, tperm, ye, xe);
     for (size_t q = lv.steps.size(); q-- > 0;) {
       const SolveStep& st = lv.steps[q];
-      if (st.task_cnt > 0)
-        hipLaunchKernelGGL((k_lbwd_gemv<T>), dim3(st.task_cnt), dim3(64), 0, s, M,
-                           reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, xe, partial);
-      hipLaunchKernelGGL((k_lbwd_tile<T>), dim3(st.nfronts), dim3(64), 0, s, M, sc + lv.large_off,
-                         sc + st.prefix_off, st.t, L, tperm, ye, partial, xe);
+      hipLaunchKernelGGL((k_lbwd_step<T>), dim3(st.task_cnt), dim3(NT), 0, s, M,
+                         reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, tperm, ye, partial,
+                         counter, xe);
     }
   }
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, s, n, perm, xe, x);
@@ -369,10 +361,10 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
 template void solve_enqueue<double>(const SolvePlan&, const FrontMeta&, const double*, const double*,
                                     const double*, const int32_t*, const int64_t*, int64_t,
                                     const double*, double*, double*, double*, double*, double*,
-                                    hipStream_t);
+                                    int32_t*, hipStream_t);
 template void solve_enqueue<float>(const SolvePlan&, const FrontMeta&, const float*, const double*,
                                    const double*, const int32_t*, const int64_t*, int64_t,
                                    const double*, double*, double*, double*, double*, double*,
-                                   hipStream_t);
+                                   int32_t*, hipStream_t);
 
 }  // namespace kth

@@ -12,8 +12,8 @@ namespace kth {
 struct SolveStep {
   int32_t t;
   int32_t nfronts;               // active large fronts (prefix of the level's list)
-  int32_t task_off, task_cnt;    // Int2 (front, row) tasks of kTrsmRows rows below the tile
-  int32_t prefix_off;            // [nfronts+1] task ranges per active front
+  int32_t task_off, task_cnt;    // Int2 (front, first row) tasks of kSolveRows rows below the
+                                 // tile, in row order per front; (front, nf) if none
 };
 
 struct SolveLevel {
@@ -31,11 +31,12 @@ struct SolvePlan {
 
 // x = (A - sigma B)^{-1} b with a kept factor (T = double or float panels).
 // xe, ye: n-vectors of scratch; R: work vectors (rows.size() doubles);
-// partial: P.partial_size doubles.
+// partial: P.partial_size doubles; counter: one int32 per supernode, zero on entry
+// (and on exit).
 template <typename T>
 void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const double* D,
                    const double* E, const int32_t* tperm, const int64_t* perm, int64_t n,
                    const double* b, double* x, double* xe, double* ye, double* R, double* partial,
-                   hipStream_t s);
+                   int32_t* counter, hipStream_t s);
 
 }  // namespace kth
