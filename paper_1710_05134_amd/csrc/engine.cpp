@@ -105,7 +105,6 @@ static void build_schedule(Pencil& P) {
       sp.trsm_cnt = (int32_t)((sched.size() - sp.trsm_off) / 2);
       sp.trsm_prefix_off = (int32_t)sched.size();
       sched.insert(sched.end(), tpre.begin(), tpre.end());
-      P.splan.partial_size = std::max<int64_t>(P.splan.partial_size, (int64_t)sp.trsm_cnt * kNB);
       sp.prefix_off = (int32_t)sched.size();
       int64_t tot = 0;
       for (int32_t q = 0; q < act; q++) {
@@ -124,6 +123,8 @@ static void build_schedule(Pencil& P) {
       lp.steps.push_back(sp);
     }
   }
+  std::vector<int64_t> pbase(S.nsup, -1);
+  P.splan.partial_half = 0;
   // solve plan: small fronts reuse the factorization lists; large fronts get
   // gather tasks of kSolveChunk rows and reuse the panel tasks of each step
   P.splan.levels.assign(S.nlevels, SolveLevel());
@@ -155,17 +156,28 @@ static void build_schedule(Pencil& P) {
         for (int64_t r = rb; r < nf; r += kSolveRows) { sched.push_back(s); sched.push_back((int32_t)r); }
       }
       ss.task_cnt = (int32_t)((sched.size() - ss.task_off) / 2);
-      P.splan.partial_size = std::max<int64_t>(P.splan.partial_size, (int64_t)ss.task_cnt * kNB);
       sl.steps.push_back(ss);
     }
+    // backward partial-sum slots: front s owns as many as its step-0 row chunks
+    int64_t slots = 0;
+    for (int32_t q = 0; q < lp.large_cnt; q++) {
+      const int32_t s = sched[lp.large_off + q];
+      const int64_t ns = S.ns(s), nf = S.nf(s), rb = std::min<int64_t>(kNB, ns);
+      pbase[s] = slots;
+      slots += nf > rb ? (nf - rb + kSolveRows - 1) / kSolveRows : 1;
+    }
+    P.splan.partial_half = std::max(P.splan.partial_half, slots);
   }
+  P.splan.partial_size = std::max<int64_t>(1, 2 * P.splan.partial_half * kNB);
   Ctx* c = P.ctx;
   P.d_sched.upload(c, sched);
   P.h_sched = sched;
   P.d_wptr.upload(c, wptr);
   P.d_tptr.upload(c, tptr);
   P.d_tilew.upload(c, tilew);
+  P.d_pbase.upload(c, pbase);
   P.splan.sched = P.d_sched.get();
+  P.splan.pbase = P.d_pbase.get();
 }
 
 void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
@@ -441,17 +453,15 @@ void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x) {
     F.ye.alloc(c, (size_t)P.n);
     F.R.alloc(c, P.S.rows.size());
     F.partial.alloc(c, (size_t)P.splan.partial_size);
-    F.counter.alloc(c, (size_t)P.S.nsup);
-    KTH_HIP(hipMemsetAsync(F.counter.get(), 0, sizeof(int32_t) * P.S.nsup, c->stream));
   }
   if (F.prec == KTH_FP64)
     solve_enqueue<double>(P.splan, P.meta, F.L.get(), F.D.get(), F.E.get(), F.tperm.get(),
                           P.d_perm.get(), P.n, b, x, F.xe.get(), F.ye.get(), F.R.get(),
-                          F.partial.get(), F.counter.get(), c->stream);
+                          F.partial.get(), c->stream);
   else
     solve_enqueue<float>(P.splan, P.meta, reinterpret_cast<const float*>(F.L.get()), F.D.get(),
                          F.E.get(), F.tperm.get(), P.d_perm.get(), P.n, b, x, F.xe.get(),
-                         F.ye.get(), F.R.get(), F.partial.get(), F.counter.get(), c->stream);
+                         F.ye.get(), F.R.get(), F.partial.get(), c->stream);
 }
 
 }  // namespace kth

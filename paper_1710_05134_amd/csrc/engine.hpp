@@ -107,7 +107,7 @@ struct Pencil {
   DBuf<double> aval, bval, zeros;
   // device metadata
   DBuf<int64_t> d_sfirst, d_rptr, d_lptr, d_uptr, d_wptr, d_tptr, d_eptr, d_cptr, d_acptr, d_asrc,
-      d_adst, d_perm;
+      d_adst, d_perm, d_pbase;
   DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched;
   FrontMeta meta{};
   std::vector<LevelPlan> levels;
@@ -137,7 +137,6 @@ struct NumFactor {
   bool have_stats = false;
   // solve scratch
   DBuf<double> xe, ye, R, partial;
-  DBuf<int32_t> counter;      // per-supernode completion counters of the backward steps
   // refinement scratch (FP32 factors): residual, Krylov basis, dot partials, small results
   DBuf<double> ir_r, ir_V, ir_part, ir_out;
 };

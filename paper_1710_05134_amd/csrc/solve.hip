@@ -18,6 +18,13 @@ namespace {
 
 constexpr int NT = 256;
 
+// Value of v in lane p (p uniform across the wavefront) through two v_readlane.
+__device__ inline double lane_value(double v, int p) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), p);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), p);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ inline void tile_bounds(int t, int tw, int ns, int& k0, int& kb) {
   k0 = t * tw;
   kb = min(tw, ns - k0);
@@ -189,17 +196,41 @@ __device__ inline double apply_dinv(const double* __restrict__ D, const double* 
   return D[k] != 0.0 ? z[q] / D[k] : 0.0;
 }
 
-// Forward tile step t of the large fronts of a level, one launch: every
-// workgroup solves L_tt z = P_t r_t itself (the 64x64 tile held in registers,
-// row = lane) and subtracts L(i, tile) z from its kSolveRows rows below the tile;
-// the workgroup of a front's first row chunk also writes y = D^{-1} z.  A front
-// without rows below the tile has one task with an empty row range.
+// Sum over the 64 lanes of a wavefront of v[0..63] (lane l holds row l's products
+// with 64 columns), by recursive halving: at offset h every lane keeps one half of
+// its block of columns and adds its partner's copy of that half.  On return lane l
+// holds in v[0] the total of column l.  63 exchanges instead of 64 x 6.
+template <int H>
+__device__ inline void column_sums_step(double (&v)[kNB], int lane) {
+  const bool up = (lane & H) != 0;
+#pragma unroll
+  for (int j = 0; j < H; j++) {
+    const double keep = up ? v[j + H] : v[j];
+    const double send = up ? v[j] : v[j + H];
+    v[j] = keep + __shfl_xor(send, H);
+  }
+  if constexpr (H > 1) column_sums_step<H / 2>(v, lane);
+}
+
+__device__ inline void wave_column_sums(double (&v)[kNB], int lane) {
+  column_sums_step<kNB / 2>(v, lane);
+}
+
+constexpr int kFwdThreads = 64 + kSolveRows;   // wave 0: tile solve; the rest: one row each
+constexpr int kBwdThreads = kSolveRows;        // one row each (four waves)
+
+// Forward tile step t of the large fronts of a level, one launch.  Every
+// workgroup solves L_tt z = P_t r_t itself (wave 0, the 64x64 tile in registers,
+// row = lane) while its other waves load their rows' 64 entries of L below the
+// tile; then R_i -= L(i, tile) z for its kSolveRows rows.  The workgroup of a
+// front's first row chunk also writes y = D^{-1} z.  A front without rows below
+// the tile has one task with an empty row range.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_lfwd_step(FrontMeta M, const Int2* tasks, int t,
-                                                  const T* L, const double* __restrict__ D,
-                                                  const double* __restrict__ E,
-                                                  const int32_t* __restrict__ tperm, double* R,
-                                                  double* ye) {
+__global__ __launch_bounds__(kFwdThreads) void k_lfwd_step(FrontMeta M, const Int2* tasks, int t,
+                                                           const T* L, const double* __restrict__ D,
+                                                           const double* __restrict__ E,
+                                                           const int32_t* __restrict__ tperm,
+                                                           double* R, double* ye) {
   __shared__ double z[kNB];
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, r0 = tk.b;
@@ -210,44 +241,98 @@ __global__ __launch_bounds__(NT) void k_lfwd_step(FrontMeta M, const Int2* tasks
   const int k0 = t * kNB, kb = min(kNB, ns - k0);
   const T* Lp = L + M.lptr[s];
   double* Rs = R + M.rptr[s];
+  double Lv[kNB];
+  const int i = r0 + tid - 64;
+  // unconditional loads from clamped (valid) addresses, masked afterwards, so that
+  // all 64 are in flight together
   if (tid < 64) {
-    double Lr[kNB];
+    const int lc = min(lane, kb - 1);
 #pragma unroll
-    for (int p = 0; p < kNB; p++)
-      Lr[p] = (lane < kb && p < kb) ? (double)Lp[(k0 + lane) + (int64_t)(k0 + p) * nf] : 0.0;
+    for (int p = 0; p < kNB; p++) Lv[p] = (double)Lp[(k0 + lc) + (int64_t)(k0 + min(p, kb - 1)) * nf];
+    // strictly lower part of the tile only, so that every step updates all lanes
+#pragma unroll
+    for (int p = 0; p < kNB; p++) Lv[p] = (lane < kb && p < lane) ? Lv[p] : 0.0;
     double zl = lane < kb ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
 #pragma unroll
-    for (int p = 0; p < kNB; p++) {
-      const double zp = __shfl(zl, p);
-      if (lane > p) zl -= Lr[p] * zp;   // Lr[p] = 0 beyond the tile
-    }
+    for (int p = 0; p < kNB; p++) zl = fma(-Lv[p], lane_value(zl, p), zl);
     z[lane] = zl;
+  } else {
+    const int ic = min(i, nf - 1);
+#pragma unroll
+    for (int q = 0; q < kNB; q++) Lv[q] = (double)Lp[ic + (int64_t)(k0 + min(q, kb - 1)) * nf];
+#pragma unroll
+    for (int q = 0; q < kNB; q++) Lv[q] = q < kb ? Lv[q] : 0.0;
   }
   __syncthreads();
-  const int i = r0 + tid;
-  if (tid < kSolveRows && i < nf) {
+  if (tid >= 64 && i < nf) {
     double acc = 0.0;
-    for (int q = 0; q < kb; q++) acc = fma((double)Lp[i + (int64_t)(k0 + q) * nf], z[q], acc);
+#pragma unroll
+    for (int q = 0; q < kNB; q++) acc = fma(Lv[q], z[q], acc);
     Rs[i] -= acc;
   }
   if (r0 == k0 + kb && tid < kb) ye[f0 + k0 + tid] = apply_dinv(D, E, z, f0 + k0 + tid, tid, kb);
 }
 
-// Backward tile step t (tiles in reverse), one launch: every workgroup forms
-// partial[task][q] = sum over its rows i of L(i, k0+q) x(rows[i]) (lane = column,
-// four waves over the rows); the last workgroup of a front to finish (counted
-// with a device-scope atomic after a release fence, then an acquire fence) adds
-// the front's partials in task order, solves L_tt^T w = y_t - partial sum with
-// the tile in registers (column = lane) and writes x(f0 + k0 + perm[q]) = w_q;
-// it also resets the front's counter for the next step.
+// Backward, tile t of front s: w = L_tt^{-T} (y_t - sum of the front's partial
+// column sums of step t, in chunk order), x(f0 + k0 + perm[q]) = w_q.  Called by
+// all threads of a workgroup; tl: LDS staging of the tile (row-major, padded).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_lbwd_step(FrontMeta M, const Int2* tasks, int t,
-                                                  const T* L, const int32_t* __restrict__ tperm,
-                                                  const double* __restrict__ ye, double* partial,
-                                                  int32_t* counter, double* xe) {
-  __shared__ double wsum[NT / 64][kNB];
-  __shared__ double xv[kSolveRows];
-  __shared__ int last;
+__device__ inline void bwd_finish_tile(const FrontMeta& M, int s, int t, const T* L,
+                                       const int32_t* __restrict__ tperm,
+                                       const double* __restrict__ ye, const double* partial,
+                                       double* xe, double (&tl)[kNB][kNB + 1]) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB, kb = min(kNB, ns - k0), rb = k0 + kb;
+  const int ntask = nf > rb ? (nf - rb + kSolveRows - 1) / kSolveRows : 1;
+  const T* Lp = L + M.lptr[s];
+  for (int e = tid; e < kNB * kNB; e += blockDim.x) {
+    const int r = e & 63, c = e >> 6;
+    tl[r][c] = (r < kb && c < kb) ? (double)Lp[(k0 + r) + (int64_t)(k0 + c) * nf] : 0.0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // partial sums in chunk order, loaded eight at a time
+    double acc = 0.0;
+    for (int j0 = 0; j0 < ntask; j0 += 8) {
+      double pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) pv[u] = partial[(int64_t)min(j0 + u, ntask - 1) * kNB + lane];
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+        if (j0 + u < ntask) acc += pv[u];
+    }
+    double g = lane < kb ? ye[f0 + k0 + lane] - acc : 0.0;
+    // column lane of the tile, strictly below the diagonal
+    double Lc[kNB];
+#pragma unroll
+    for (int p = 0; p < kNB; p++) Lc[p] = p > lane ? tl[p][lane] : 0.0;
+#pragma unroll
+    for (int p = kNB - 1; p >= 0; p--) g = fma(-Lc[p], lane_value(g, p), g);
+    if (lane < kb) xe[f0 + k0 + tperm[f0 + k0 + lane]] = g;
+  }
+  __syncthreads();
+}
+
+// Backward tile step t (tiles in reverse), one launch, no inter-workgroup
+// synchronisation: the workgroup of a front's first row chunk first finishes tile
+// t+1 (whose rows open its chunk) from the partial sums the previous launch left;
+// then every workgroup stores the column sums sum_i L(i, k0+q) x(rows[i]) of its
+// kSolveRows rows (row = thread, coalesced loads, wave_column_sums) in the front's
+// slot for this step's parity.  Tile 0 is finished by k_lbwd_finish.
+// partial: [2][slots][kNB]; pbase[s]: the front's first slot (its chunk j at +j).
+template <typename T>
+__global__ __launch_bounds__(kBwdThreads) void k_lbwd_step(FrontMeta M, const Int2* tasks, int t,
+                                                           const T* L,
+                                                           const int32_t* __restrict__ tperm,
+                                                           const double* __restrict__ ye,
+                                                           const int64_t* __restrict__ pbase,
+                                                           int64_t half, double* partial,
+                                                           double* xe) {
+  __shared__ double wsum[kBwdThreads / 64][kNB];
+  __shared__ double tl[kNB][kNB + 1];
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, r0 = tk.b;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -256,52 +341,45 @@ __global__ __launch_bounds__(NT) void k_lbwd_step(FrontMeta M, const Int2* tasks
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
   const int k0 = t * kNB, kb = min(kNB, ns - k0);
   const int rb = k0 + kb;                      // first row below the tile
-  const int nr = max(0, min(kSolveRows, nf - r0));
+  const int64_t pb = pbase[s];
+  if (r0 == rb && rb < ns)                     // tile t+1 exists and opens this chunk
+    bwd_finish_tile(M, s, t + 1, L, tperm, ye, partial + (((t + 1) & 1) * half + pb) * kNB, xe, tl);
   const T* Lp = L + M.lptr[s];
-  const int32_t* rows = M.rows + M.rptr[s];
-  if (tid < kSolveRows) xv[tid] = tid < nr ? xe[rows[r0 + tid]] : 0.0;
-  __syncthreads();
+  const int i = r0 + tid;
   {
-    double acc = 0.0;
-    const int rw0 = wave * (kSolveRows / (NT / 64));
-    const int rw1 = min(rw0 + kSolveRows / (NT / 64), nr);
-    if (lane < kb)
-      for (int r = rw0; r < rw1; r++)
-        acc = fma((double)Lp[(r0 + r) + (int64_t)(k0 + lane) * nf], xv[r], acc);
-    wsum[wave][lane] = acc;
+    // unconditional loads from clamped (valid) addresses, masked afterwards, so
+    // that all 64 are in flight together
+    const int ic = min(i, nf - 1);
+    const double xi = i < nf ? xe[M.rows[M.rptr[s] + ic]] : 0.0;
+    double v[kNB];
+#pragma unroll
+    for (int q = 0; q < kNB; q++) v[q] = (double)Lp[ic + (int64_t)(k0 + min(q, kb - 1)) * nf];
+#pragma unroll
+    for (int q = 0; q < kNB; q++) v[q] = q < kb ? v[q] * xi : 0.0;
+    wave_column_sums(v, lane);
+    wsum[wave][lane] = v[0];
   }
   __syncthreads();
-  const int ntask = nf > rb ? (nf - rb + kSolveRows - 1) / kSolveRows : 1;
-  const int first = (int)blockIdx.x - (r0 - rb) / kSolveRows;
   if (tid < 64) {
-    double v = 0.0;
-    for (int w = 0; w < NT / 64; w++) v += wsum[w][lane];
-    partial[(int64_t)blockIdx.x * kNB + lane] = v;
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) last = atomicAdd(&counter[s], 1) == ntask - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (tid == 0) atomicExch(&counter[s], 0);
-  if (tid >= 64) return;
-  double g = 0.0;
-  if (lane < kb) {
     double acc = 0.0;
-    for (int q = first; q < first + ntask; q++) acc += partial[(int64_t)q * kNB + lane];
-    g = ye[f0 + k0 + lane] - acc;
-  }
-  double Lc[kNB];
 #pragma unroll
-  for (int p = 0; p < kNB; p++)
-    Lc[p] = (lane < kb && p < kb) ? (double)Lp[(k0 + p) + (int64_t)(k0 + lane) * nf] : 0.0;
-#pragma unroll
-  for (int p = kNB - 1; p >= 0; p--) {
-    const double wp = __shfl(g, p);
-    if (lane < p) g -= Lc[p] * wp;   // Lc[p] = 0 beyond the tile
+    for (int w = 0; w < kBwdThreads / 64; w++) acc += wsum[w][lane];
+    const int j = (r0 - rb) / kSolveRows;
+    partial[((t & 1) * half + pb + j) * kNB + lane] = acc;
   }
-  if (lane < kb) xe[f0 + k0 + tperm[f0 + k0 + lane]] = g;
+}
+
+// Backward: tile 0 of every large front of a level (one workgroup per front).
+template <typename T>
+__global__ __launch_bounds__(kBwdThreads) void k_lbwd_finish(FrontMeta M, const int32_t* fronts,
+                                                             const T* L,
+                                                             const int32_t* __restrict__ tperm,
+                                                             const double* __restrict__ ye,
+                                                             const int64_t* __restrict__ pbase,
+                                                             const double* partial, double* xe) {
+  __shared__ double tl[kNB][kNB + 1];
+  const int s = fronts[blockIdx.x];
+  bwd_finish_tile(M, s, 0, L, tperm, ye, partial + pbase[s] * kNB, xe, tl);
 }
 
 __global__ void k_gather(int64_t n, const int64_t* __restrict__ perm, const double* __restrict__ x,
@@ -329,7 +407,7 @@ template <typename T>
 void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const double* D,
                    const double* E, const int32_t* tperm, const int64_t* perm, int64_t n,
                    const double* b, double* x, double* xe, double* ye, double* R, double* partial,
-                   int32_t* counter, hipStream_t s) {
+                   hipStream_t s) {
   const int32_t* sc = P.sched;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(256), 0, s, n, perm, b, xe);
   for (const SolveLevel& lv : P.levels) {
@@ -340,7 +418,7 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
     hipLaunchKernelGGL((k_lfwd_init<T>), dim3(lv.init_cnt), dim3(NT), 0, s, M,
                        reinterpret_cast<const Int2*>(sc + lv.init_off), xe, R);
     for (const SolveStep& st : lv.steps)
-      hipLaunchKernelGGL((k_lfwd_step<T>), dim3(st.task_cnt), dim3(NT), 0, s, M,
+      hipLaunchKernelGGL((k_lfwd_step<T>), dim3(st.task_cnt), dim3(kFwdThreads), 0, s, M,
                          reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, D, E, tperm, R, ye);
   }
   for (size_t l = P.levels.size(); l-- > 0;) {
@@ -350,10 +428,13 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
                          L, tperm, ye, xe);
     for (size_t q = lv.steps.size(); q-- > 0;) {
       const SolveStep& st = lv.steps[q];
-      hipLaunchKernelGGL((k_lbwd_step<T>), dim3(st.task_cnt), dim3(NT), 0, s, M,
-                         reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, tperm, ye, partial,
-                         counter, xe);
+      hipLaunchKernelGGL((k_lbwd_step<T>), dim3(st.task_cnt), dim3(kBwdThreads), 0, s, M,
+                         reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, tperm, ye,
+                         P.pbase, P.partial_half, partial, xe);
     }
+    if (lv.large_cnt > 0)
+      hipLaunchKernelGGL((k_lbwd_finish<T>), dim3(lv.large_cnt), dim3(kBwdThreads), 0, s, M,
+                         sc + lv.large_off, L, tperm, ye, P.pbase, partial, xe);
   }
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, s, n, perm, xe, x);
 }
@@ -361,10 +442,10 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
 template void solve_enqueue<double>(const SolvePlan&, const FrontMeta&, const double*, const double*,
                                     const double*, const int32_t*, const int64_t*, int64_t,
                                     const double*, double*, double*, double*, double*, double*,
-                                    int32_t*, hipStream_t);
+                                    hipStream_t);
 template void solve_enqueue<float>(const SolvePlan&, const FrontMeta&, const float*, const double*,
                                    const double*, const int32_t*, const int64_t*, int64_t,
                                    const double*, double*, double*, double*, double*, double*,
-                                   int32_t*, hipStream_t);
+                                   hipStream_t);
 
 }  // namespace kth

@@ -26,17 +26,18 @@ struct SolveLevel {
 struct SolvePlan {
   const int32_t* sched = nullptr;    // device int32 schedule array
   std::vector<SolveLevel> levels;
-  int64_t partial_size = 1;          // doubles for the backward partial sums
+  int64_t partial_size = 1;          // doubles for the backward partial sums: 2 * half * kNB
+  int64_t partial_half = 0;          // slots per step parity (max over levels)
+  const int64_t* pbase = nullptr;    // device [nsup]: a large front's first slot in its level
 };
 
 // x = (A - sigma B)^{-1} b with a kept factor (T = double or float panels).
 // xe, ye: n-vectors of scratch; R: work vectors (rows.size() doubles);
-// partial: P.partial_size doubles; counter: one int32 per supernode, zero on entry
-// (and on exit).
+// partial: P.partial_size doubles.
 template <typename T>
 void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const double* D,
                    const double* E, const int32_t* tperm, const int64_t* perm, int64_t n,
                    const double* b, double* x, double* xe, double* ye, double* R, double* partial,
-                   int32_t* counter, hipStream_t s);
+                   hipStream_t s);
 
 }  // namespace kth
