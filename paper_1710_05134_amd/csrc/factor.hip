@@ -27,6 +27,44 @@ constexpr double kAlphaBK = 0.6403882032022076;  // (1 + sqrt(17)) / 8
 
 __device__ inline unsigned long long dbits(double x) { return __double_as_longlong(x); }
 
+// 64-bit lane exchange by DPP (CTRL: a quad_perm or row-mirror control word).
+template <int CTRL>
+__device__ inline unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(v & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+__device__ inline unsigned long long readlane_u64(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Maximum of v over the 64 lanes, returned to every lane: DPP swaps within quads
+// (xor 1, xor 2), half rows and rows (mirrors), then the four row maxima.
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+  unsigned long long o;
+  o = dpp_u64<0xB1>(v); v = o > v ? o : v;    // quad_perm [1,0,3,2]
+  o = dpp_u64<0x4E>(v); v = o > v ? o : v;    // quad_perm [2,3,0,1]
+  o = dpp_u64<0x141>(v); v = o > v ? o : v;   // row_half_mirror
+  o = dpp_u64<0x140>(v); v = o > v ? o : v;   // row_mirror
+  const unsigned long long a = readlane_u64(v, 0), b = readlane_u64(v, 16);
+  const unsigned long long c = readlane_u64(v, 32), d = readlane_u64(v, 48);
+  const unsigned long long ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
+// Value of v in lane p (p uniform) through v_readlane.
+__device__ inline double lane_value(double v, int p) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), p);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), p);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float lane_value(float v, int p) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), p));
+}
+
 // Block-wide argmax of (v, idx): larger v wins, ties -> smaller idx (idx -1 = none).
 template <int NT>
 __device__ inline void block_argmax(double& v, int& idx, double* sv, int* si) {
@@ -266,47 +304,66 @@ __device__ void bk_factor_lds(T* F, int ld, int nrows, int ncand, int* lp, T* d,
   if (tid == 0) cnt.maxl = fmax(cnt.maxl, maxl);
 }
 
-// Bunch-Kaufman LDL^T of one kb x kb pivot tile (kb <= kNB) in LDS, by 4 wavefronts:
-// wave 0 searches pivots (lanes = rows, shuffle reductions), every wave updates a
-// quarter of the columns of each row (lane = row, wave = column residue mod 4).
+// Symmetric interchange of indices a < r of a pivot tile in the middle of its
+// factorization at step k: the trailing lower triangle (columns >= k) lives in F,
+// the finished multiplier columns (< k) in Lo.
 template <typename T>
-__device__ void bk_tile_lds(T* F, int ld, int kb, int* lp, T* d, T* e,
-                            T* lcol, BKCounts& cnt, int* dec) {
+__device__ inline void tile_sym_swap(T* F, T* Lo, int ld, int kb, int k, int a, int r) {
+  for (int x = threadIdx.x; x < kb - 1; x += blockDim.x) {
+    if (x < a) {
+      T* M = x < k ? Lo : F;
+      T t = M[a + x * ld]; M[a + x * ld] = M[r + x * ld]; M[r + x * ld] = t;
+    } else if (x == a) {
+      T t = F[a + a * ld]; F[a + a * ld] = F[r + r * ld]; F[r + r * ld] = t;
+    } else if (x < r) {
+      T t = F[x + a * ld]; F[x + a * ld] = F[r + x * ld]; F[r + x * ld] = t;
+    } else {
+      int i = x + 1;
+      T t = F[i + a * ld]; F[i + a * ld] = F[i + r * ld]; F[i + r * ld] = t;
+    }
+  }
+}
+
+// Bunch-Kaufman LDL^T of one kb x kb pivot tile (kb <= kNB) in LDS by 4 wavefronts.
+// Every wave finds the pivot itself (lanes = rows, DPP maxima), so the decision
+// needs no broadcast; lane i of wave w forms row i's multipliers and updates the
+// columns j = w (mod 4) of row i.  Multipliers go to Lo (zeroed here; strictly
+// below the diagonal, 0 inside 2x2 blocks); F keeps the unscaled trailing matrix.
+// Two barriers per pivot step (after the search, after the update), three with an
+// interchange.
+template <typename T>
+__device__ void bk_tile_lds(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, BKCounts& cnt) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane;
   double maxl = 0.0;
   if (tid < kNB) lp[tid] = tid;
+  for (int x = tid; x < kNB * kNB; x += blockDim.x) Lo[(x & 63) + (x >> 6) * ld] = 0.0;
   __syncthreads();
   int k = 0;
   while (k < kb) {
-    if (wave == 0) {
-      // gamma_1 and its row r among the candidates k < i < kb (ties: smallest row)
-      unsigned long long key = 0;
-      const int i = lane;
-      if (i > k && i < kb)
-        key = (dbits(fabs((double)F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
-      for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long o = __shfl_xor(key, off);
-        key = o > key ? o : key;
-      }
-      const int r = key == 0 ? k : 128 - (int)(key & 0xFFull);
-      const double g1 = key == 0 ? 0.0 : fabs((double)F[r + k * ld]);
-      const double akk = fabs((double)F[k + k * ld]);
-      int kind = 0;
-      if (!(g1 == 0.0 || akk >= kAlphaBK * g1)) {
-        double gv = 0.0;
-        if (i >= k && i < kb && i != r) gv = i < r ? fabs((double)F[r + i * ld]) : fabs((double)F[i + r * ld]);
-        for (int off = 32; off > 0; off >>= 1) gv = fmax(gv, __shfl_xor(gv, off));
-        if (akk * gv >= kAlphaBK * g1 * g1) kind = 0;
-        else if (fabs((double)F[r + r * ld]) >= kAlphaBK * gv) kind = 1;
-        else kind = 2;
-      }
-      if (lane == 0) { dec[0] = kind; dec[1] = r; }
+    // gamma_1 and its row r among the candidates k < i < kb (ties: smallest row)
+    unsigned long long key = 0;
+    if (i > k && i < kb)
+      key = (dbits(fabs((double)F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
+    key = wave_max_u64(key);
+    const int r = key == 0 ? k : 128 - (int)(key & 0xFFull);
+    const double g1 = key == 0 ? 0.0 : fabs((double)F[r + k * ld]);
+    const double akk = fabs((double)F[k + k * ld]);
+    int kind = 0;
+    if (!(g1 == 0.0 || akk >= kAlphaBK * g1)) {
+      unsigned long long gb = 0;   // |.| >= 0: bit patterns order as the values
+      if (i >= k && i < kb && i != r)
+        gb = dbits(i < r ? fabs((double)F[r + i * ld]) : fabs((double)F[i + r * ld]));
+      const double gr = __longlong_as_double((long long)wave_max_u64(gb));
+      if (akk * gr >= kAlphaBK * g1 * g1) kind = 0;
+      else if (fabs((double)F[r + r * ld]) >= kAlphaBK * gr) kind = 1;
+      else kind = 2;
     }
+    // every wave has finished its search reads before any entry moves or changes
     __syncthreads();
-    const int kind = dec[0], r = dec[1];
     if (kind == 1 || (kind == 2 && r != k + 1)) {
       const int a = kind == 1 ? k : k + 1;
-      lds_sym_swap<256, T>(F, ld, kb, a, r);
+      tile_sym_swap<T>(F, Lo, ld, kb, k, a, r);
       if (tid == 0) { int t = lp[a]; lp[a] = lp[r]; lp[r] = t; }
       __syncthreads();
     }
@@ -317,21 +374,11 @@ __device__ void bk_tile_lds(T* F, int ld, int kb, int* lp, T* d, T* e,
         if (dk < 0) cnt.neg++; else if (dk > 0) cnt.pos++; else cnt.zero++;
         cnt.mind = fmin(cnt.mind, fabs((double)dk));
       }
-      if (wave == 0 && lane > k && lane < kb) lcol[lane] = dk != 0.0 ? F[lane + k * ld] / dk : 0.0;
-      __syncthreads();
-      if (dk != 0.0) {
-        const int i = lane;
-        if (i > k && i < kb) {
-          const T li = lcol[i];
-          for (int j = k + 1 + wave; j <= i; j += 4) F[i + j * ld] -= li * F[j + k * ld];
-        }
+      if (dk != 0.0 && i > k && i < kb) {
+        const T li = F[i + k * ld] / dk;
+        for (int j = k + 1 + wave; j <= i; j += 4) F[i + j * ld] -= li * F[j + k * ld];
+        if (wave == 0) { Lo[i + k * ld] = li; maxl = fmax(maxl, fabs((double)li)); }
       }
-      __syncthreads();
-      if (wave == 0 && lane > k && lane < kb) {
-        F[lane + k * ld] = lcol[lane];
-        maxl = fmax(maxl, fabs((double)lcol[lane]));
-      }
-      if (tid == 0) F[k + k * ld] = 1.0;
       __syncthreads();
       k += 1;
     } else {
@@ -347,28 +394,17 @@ __device__ void bk_tile_lds(T* F, int ld, int kb, int* lp, T* d, T* e,
         const T m = 0.5 * tr, q = sqrt(0.25 * (a - c) * (a - c) + b * b);
         cnt.mind = fmin(cnt.mind, fmin(fabs((double)m - q), fabs((double)m + q)));
       }
-      T* lcol2 = lcol + kNB;
-      if (wave == 0 && lane > k + 1 && lane < kb) {
-        const T w1 = F[lane + k * ld], w2 = F[lane + (k + 1) * ld];
-        lcol[lane] = (c * w1 - b * w2) / det;
-        lcol2[lane] = (a * w2 - b * w1) / det;
-      }
-      __syncthreads();
-      {
-        const int i = lane;
-        if (i > k + 1 && i < kb) {
-          const T l1 = lcol[i], l2 = lcol2[i];
-          for (int j = k + 2 + wave; j <= i; j += 4)
-            F[i + j * ld] -= l1 * F[j + k * ld] + l2 * F[j + (k + 1) * ld];
+      if (i > k + 1 && i < kb) {
+        const T w1 = F[i + k * ld], w2 = F[i + (k + 1) * ld];
+        const T l1 = (c * w1 - b * w2) / det, l2 = (a * w2 - b * w1) / det;
+        for (int j = k + 2 + wave; j <= i; j += 4)
+          F[i + j * ld] -= l1 * F[j + k * ld] + l2 * F[j + (k + 1) * ld];
+        if (wave == 0) {
+          Lo[i + k * ld] = l1;
+          Lo[i + (k + 1) * ld] = l2;
+          maxl = fmax(maxl, fmax(fabs((double)l1), fabs((double)l2)));
         }
       }
-      __syncthreads();
-      if (wave == 0 && lane > k + 1 && lane < kb) {
-        F[lane + k * ld] = lcol[lane];
-        F[lane + (k + 1) * ld] = lcol2[lane];
-        maxl = fmax(maxl, fmax(fabs((double)lcol[lane]), fabs((double)lcol2[lane])));
-      }
-      if (tid == 0) { F[k + k * ld] = 1.0; F[(k + 1) + k * ld] = 0.0; F[(k + 1) + (k + 1) * ld] = 1.0; }
       __syncthreads();
       k += 2;
     }
@@ -549,16 +585,12 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
     tinv += bidx * bt.sT; st += bidx;
   }
   constexpr int LD = kNB + 1;   // padded: row walks across lanes hit distinct LDS banks
-  __shared__ T Tl[kNB * LD];
-  __shared__ T Linv[kNB * LD];
-  __shared__ double sv[(NT + 63) / 64];
-  __shared__ int si[(NT + 63) / 64];
+  __shared__ T Tl[kNB * LD];    // the tile; after the factorization, the inverse of L_tt
+  __shared__ T Lo[kNB * LD];    // multipliers (strictly lower part of L_tt)
   __shared__ int lp[kNB];
   __shared__ T dd[kNB], ee[kNB];
-  __shared__ T lcol[2 * kNB];
-  __shared__ int dec[2];
   const int s = fronts[blockIdx.x];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
@@ -582,20 +614,20 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
   }
   __syncthreads();
   BKCounts cnt{0, 0, 0, 0, INFINITY, 0.0};
-  bk_tile_lds<T>(Tl, LD, kb, lp, dd, ee, lcol, cnt, dec);
-  __syncthreads();
+  bk_tile_lds<T>(Tl, Lo, LD, kb, lp, dd, ee, cnt);
+  // unit-lower L_tt back to the panel (ones on the diagonal, zeros inside 2x2 blocks)
   for (int x0 = 0; x0 < kb * kb; x0 += NT * U) {
     T v[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = x0 + u * NT + tid;
-      v[u] = x < kb * kb ? Tl[(x % kb) + (x / kb) * LD] : 0.0;
+      v[u] = x < kb * kb ? Lo[(x % kb) + (x / kb) * LD] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = x0 + u * NT + tid;
       const int i = x % kb, j = x / kb;
-      if (x < kb * kb && i >= j) Lp[(k0 + i) + (int64_t)(k0 + j) * nf] = v[u];
+      if (x < kb * kb && i >= j) Lp[(k0 + i) + (int64_t)(k0 + j) * nf] = i == j ? (T)1.0 : v[u];
     }
   }
   for (int q = tid; q < kb; q += NT) {
@@ -603,21 +635,28 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
     E[f0 + k0 + q] = ee[q];
     tperm[f0 + k0 + q] = lp[q];
   }
-  // inverse of the unit-lower tile factor in LDS (zero-padded to kNB), axpy form:
-  // Linv = I; for p: Linv(r, c) -= L(r, p) Linv(p, c) for r > p >= c -- row p of
-  // Linv is final once step p starts; then one coalesced copy to the tile slot
-  for (int x = tid; x < kNB * kNB; x += NT) {
-    const int r = x % kNB, c = x / kNB;
-    Linv[r + c * LD] = r == c ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int p = 0; p + 1 < kb; p++) {
-    const int w = p + 1, cnt2 = (kb - 1 - p) * w;
-    for (int x = tid; x < cnt2; x += NT) {
-      const int r = p + 1 + x / w, c = x % w;
-      Linv[r + c * LD] -= Tl[r + p * LD] * Linv[p + c * LD];
+  // inverse of the unit-lower tile factor (identity beyond kb): column c of
+  // L_tt^{-1} by forward substitution, row r = lane holding L(r, p < r) in
+  // registers; wave w takes the columns c = w (mod 4), four chains at a time
+  {
+    T Lv[kNB];
+#pragma unroll
+    for (int p = 0; p < kNB; p++) Lv[p] = Lo[lane + p * LD];
+#pragma unroll 1
+    for (int c0 = wave; c0 < kNB; c0 += 16) {
+      T x0 = lane == c0, x1 = lane == c0 + 4, x2 = lane == c0 + 8, x3 = lane == c0 + 12;
+#pragma unroll
+      for (int p = 0; p < kNB; p++) {
+        x0 = fma(-Lv[p], lane_value(x0, p), x0);
+        x1 = fma(-Lv[p], lane_value(x1, p), x1);
+        x2 = fma(-Lv[p], lane_value(x2, p), x2);
+        x3 = fma(-Lv[p], lane_value(x3, p), x3);
+      }
+      Tl[lane + c0 * LD] = x0;
+      Tl[lane + (c0 + 4) * LD] = x1;
+      Tl[lane + (c0 + 8) * LD] = x2;
+      Tl[lane + (c0 + 12) * LD] = x3;
     }
-    __syncthreads();
   }
   __syncthreads();
   T* Ti = tinv + M.tptr[s];
@@ -626,7 +665,7 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = x0 + u * NT + tid;
-      v[u] = Linv[(x % kNB) + (x / kNB) * LD];
+      v[u] = Tl[(x % kNB) + (x / kNB) * LD];
     }
 #pragma unroll
     for (int u = 0; u < U; u++) Ti[x0 + u * NT + tid] = v[u];
