@@ -68,6 +68,8 @@ void check_opts(const kth_opts& o) {
 
 void ctx_release(kth_ctx_s* c) {
   if (--c->refs > 0) return;
+  (void)hipSetDevice(c->c.device);
+  c->c.destroy_aux();
   if (c->c.own_stream) (void)hipStreamDestroy(c->c.stream);
   delete c;
 }

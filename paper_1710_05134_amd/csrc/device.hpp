@@ -84,9 +84,11 @@ void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int
                        const Batch& bt, int nb, T* L, T* W, const double* D, const double* E,
                        const int32_t* tperm, const T* tinv, FactStats* st, hipStream_t s);
 template <typename T>
+// mode 0: every tile of the trailing lower triangles; 1: only the diagonal block of
+// each front's next pivot tile (grid = nfronts); 2: all but that block.
 void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
-                  int32_t nfronts, int32_t ntiles, int32_t t, const Batch& bt, int nb, T* L, T* U,
-                  const T* W, hipStream_t s);
+                  int32_t nfronts, int32_t ntiles, int32_t t, int mode, const Batch& bt, int nb,
+                  T* L, T* U, const T* W, hipStream_t s);
 void launch_set_scalar(double* p, double v, hipStream_t s);
 void launch_set_scalars(double* p, int n, const double* values, hipStream_t s);
 // MFMA operand-layout probe (tests only): D = A(16x4) * B(4x16) via one instruction.

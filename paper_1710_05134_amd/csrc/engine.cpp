@@ -32,6 +32,22 @@ void Ctx::release(void* p, size_t bytes) {
 
 void Ctx::sync() { KTH_HIP(hipStreamSynchronize(stream)); }
 
+void Ctx::ensure_aux() {
+  if (aux) return;
+  KTH_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+  KTH_HIP(hipEventCreateWithFlags(&ev_diag, hipEventDisableTiming));
+  KTH_HIP(hipEventCreateWithFlags(&ev_tile, hipEventDisableTiming));
+}
+
+void Ctx::destroy_aux() {
+  if (!aux) return;
+  (void)hipStreamSynchronize(aux);
+  (void)hipEventDestroy(ev_diag);
+  (void)hipEventDestroy(ev_tile);
+  (void)hipStreamDestroy(aux);
+  aux = nullptr;
+}
+
 static double csr_norm_inf(int64_t n, const int64_t* rp, const double* v) {
   double m = 0;
   for (int64_t i = 0; i < n; i++) {
@@ -352,6 +368,7 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
   bt.sN = P.n;
   bt.sig = F.sig.get();
   const int32_t* sched = P.d_sched.get();
+  c->ensure_aux();
   T* Lf = reinterpret_cast<T*>(F.L.get());
   T* Uf = reinterpret_cast<T*>(P.U.get());
   T* Wf = reinterpret_cast<T*>(P.W.get());
@@ -376,22 +393,32 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
       launch_front_init(P.meta, reinterpret_cast<const Int2*>(sched + lp.init_off), lp.init_cnt, av,
                         bv, bt, nb, Lf, Uf, st);
     }
-    for (const StepPlan& sp : lp.steps) {
-      double fl_tile = 0, fl_trsm = 0, fl_schur = 0;
-      if (prof)
-        for (int32_t q = 0; q < sp.nfronts; q++) {
-          const int32_t s = hs[lp.large_off + q];
-          const double ns = (double)S.ns(s), nf = (double)S.nf(s);
-          const double k0 = (double)sp.t * kNB, kb = std::min<double>(kNB, ns - k0);
-          const double R = nf - k0 - kb;   // rows below the tile
-          for (int64_t j = 0; j < (int64_t)kb; j++) { double cc = kb - 1 - j; fl_tile += cc * cc + 2 * cc; }
-          fl_trsm += R * (kb * kb + kb);      // R rows: triangular solve + diagonal scaling
-          fl_schur += kb * R * (R + 1);       // rank-kb update of the R x R lower triangle
-        }
-      {
+    // Look-ahead: after the panel solve of step q, the diagonal block of each front's
+    // next pivot tile is updated first; the next tile is then factored on the
+    // auxiliary stream while the rest of the Schur update runs on the context stream.
+    auto step_flops = [&](const StepPlan& sp, double& fl_tile, double& fl_trsm, double& fl_schur) {
+      fl_tile = fl_trsm = fl_schur = 0;
+      if (!prof) return;
+      for (int32_t q = 0; q < sp.nfronts; q++) {
+        const int32_t s = hs[lp.large_off + q];
+        const double ns = (double)S.ns(s), nf = (double)S.nf(s);
+        const double k0 = (double)sp.t * kNB, kb = std::min<double>(kNB, ns - k0);
+        const double R = nf - k0 - kb;   // rows below the tile
+        for (int64_t j = 0; j < (int64_t)kb; j++) { double cc = kb - 1 - j; fl_tile += cc * cc + 2 * cc; }
+        fl_trsm += R * (kb * kb + kb);      // R rows: triangular solve + diagonal scaling
+        fl_schur += kb * R * (R + 1);       // rank-kb update of the R x R lower triangle
+      }
+    };
+    for (size_t q = 0; q < lp.steps.size(); q++) {
+      const StepPlan& sp = lp.steps[q];
+      double fl_tile, fl_trsm, fl_schur;
+      step_flops(sp, fl_tile, fl_trsm, fl_schur);
+      if (q == 0) {
         ProfScope ps(prof, st, PROF_TILE, fl_tile);
         launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, bt, nb, Lf,
                            F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), st);
+      } else {
+        KTH_HIP(hipStreamWaitEvent(st, c->ev_tile, 0));   // tile q, factored ahead
       }
       {
         ProfScope ps(prof, st, PROF_TRSM, fl_trsm);
@@ -399,10 +426,32 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
                           sp.t, bt, nb, Lf, Wf, F.D.get(), F.E.get(), F.tperm.get(),
                           Tf, F.stats.get(), st);
       }
-      {
+      if (q + 1 < lp.steps.size()) {
+        const StepPlan& nx = lp.steps[q + 1];
+        double nt_tile, nt_trsm, nt_schur;
+        step_flops(nx, nt_tile, nt_trsm, nt_schur);
+        {
+          ProfScope ps(prof, st, PROF_SCHUR, 0.0);
+          launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
+                       sp.t, 1, bt, nb, Lf, Uf, Wf, st);
+        }
+        KTH_HIP(hipEventRecord(c->ev_diag, st));
+        KTH_HIP(hipStreamWaitEvent(c->aux, c->ev_diag, 0));
+        {
+          ProfScope ps(prof, c->aux, PROF_TILE, nt_tile);
+          launch_tile_factor(P.meta, sched + lp.large_off, nx.nfronts, nx.t, bt, nb, Lf,
+                             F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), c->aux);
+        }
+        KTH_HIP(hipEventRecord(c->ev_tile, c->aux));
+        {
+          ProfScope ps(prof, st, PROF_SCHUR, fl_schur);
+          launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
+                       sp.t, 2, bt, nb, Lf, Uf, Wf, st);
+        }
+      } else {
         ProfScope ps(prof, st, PROF_SCHUR, fl_schur);
         launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
-                     sp.t, bt, nb, Lf, Uf, Wf, st);
+                     sp.t, 0, bt, nb, Lf, Uf, Wf, st);
       }
     }
   }

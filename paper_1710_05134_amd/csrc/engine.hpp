@@ -38,9 +38,15 @@ struct Ctx {
   void* user = nullptr;
   std::string last_error;
   double cur_bytes = 0, peak_bytes = 0;
+  // second stream for the pivot tile of the next step (look-ahead), and the two
+  // events that order it against the context stream
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_diag = nullptr, ev_tile = nullptr;
   void* alloc(size_t bytes);
   void release(void* p, size_t bytes);
   void sync();
+  void ensure_aux();
+  void destroy_aux();
 };
 
 // Device buffer owned through the context's allocator.

@@ -822,24 +822,32 @@ __device__ inline void chunk_range(int c, int r0, int ns, int nf, int nc1, int& 
 template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts,
                                               const int32_t* tile_prefix, int nfronts, int t,
-                                              Batch bt, T* L, T* U, const T* W) {
+                                              int mode, Batch bt, T* L, T* U, const T* W) {
   {
     const int64_t bidx = blockIdx.y;
     L += bidx * bt.sL; U += bidx * bt.sU; W += bidx * bt.sW;
   }
   __shared__ T As[kTile * kNB];  // W rows (i) x k, ld kTile
   __shared__ T Bs[kTile * kNB];  // L rows (j) x k, ld kTile
-  // locate the front of this tile
+  // locate the front of this tile (mode 1: one workgroup per front, its tile 0)
   const int g = blockIdx.x;
   int lo = 0, hi = nfronts - 1;
-  while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (tile_prefix[mid] <= g) lo = mid; else hi = mid - 1; }
+  if (mode == 1) {
+    lo = g;
+  } else {
+    while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (tile_prefix[mid] <= g) lo = mid; else hi = mid - 1; }
+  }
   const int s = fronts[lo];
-  const int tl = g - tile_prefix[lo];
+  const int tl = mode == 1 ? 0 : g - tile_prefix[lo];
   const FrontRef<T> f = front_ref<T>(M, s, L, U);
   const int k0 = t * kNB;
   const int kb = min(kNB, f.ns - k0);
   const int r0 = k0 + kb;
   const int nc1 = r0 < f.ns ? (f.ns - r0 + kTile - 1) / kTile : 0;
+  // tile 0 of a front with a next pivot tile is that tile's diagonal block:
+  // mode 1 updates only it, mode 2 everything else, mode 0 all
+  if (mode == 1 && nc1 == 0) return;
+  if (mode == 2 && tl == 0 && nc1 > 0) return;
   // tile index -> (bi, bj), bi >= bj
   int bi = (int)((sqrt(8.0 * tl + 1.0) - 1.0) * 0.5);
   while ((bi + 1) * (bi + 2) / 2 <= tl) bi++;
@@ -1004,11 +1012,12 @@ void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int
 
 template <typename T>
 void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
-                  int32_t nfronts, int32_t ntiles, int32_t t, const Batch& bt, int nb, T* L, T* U,
-                  const T* W, hipStream_t s) {
-  if (ntiles <= 0) return;
-  hipLaunchKernelGGL((k_schur<256, T>), dim3(ntiles, nb), dim3(256), 0, s, M, fronts, tile_prefix,
-                     nfronts, t, bt, L, U, W);
+                  int32_t nfronts, int32_t ntiles, int32_t t, int mode, const Batch& bt, int nb,
+                  T* L, T* U, const T* W, hipStream_t s) {
+  const int32_t grid = mode == 1 ? nfronts : ntiles;
+  if (grid <= 0) return;
+  hipLaunchKernelGGL((k_schur<256, T>), dim3(grid, nb), dim3(256), 0, s, M, fronts, tile_prefix,
+                     nfronts, t, mode, bt, L, U, W);
 }
 
 #define KTH_INSTANTIATE_FACTOR(T)                                                                   \
@@ -1024,7 +1033,7 @@ void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile
                                      int, T*, T*, const double*, const double*, const int32_t*,     \
                                      const T*, FactStats*, hipStream_t);                            \
   template void launch_schur<T>(const FrontMeta&, const int32_t*, const int32_t*, int32_t, int32_t, \
-                                int32_t, const Batch&, int, T*, T*, const T*, hipStream_t);
+                                int32_t, int, const Batch&, int, T*, T*, const T*, hipStream_t);
 KTH_INSTANTIATE_FACTOR(double)
 KTH_INSTANTIATE_FACTOR(float)
 #undef KTH_INSTANTIATE_FACTOR
