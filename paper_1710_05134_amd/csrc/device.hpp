@@ -23,6 +23,8 @@ struct FrontMeta {
   const int64_t* adst;
   const int32_t* tilew;   // [nsup] pivot-tile width (ns for fronts factored in one piece)
   const int64_t* tptr;    // [nsup]   tile-inverse offsets (kNB*kNB per large front; -1 otherwise)
+  const int64_t* iptr;    // [nsup]   child c of a large front: offset of its inverse map (-1: none)
+  const int32_t* imap;    // inverse maps: imap[iptr[c] + i] = child row of parent row i, or -1
 };
 
 // Results of one numeric factorization that the host reads back.

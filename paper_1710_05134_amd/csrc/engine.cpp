@@ -234,6 +234,21 @@ void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const in
   P.d_asrc.upload(ctx, S.asrc);
   P.d_adst.upload(ctx, S.adst);
   P.d_perm.upload(ctx, S.perm);
+  {
+    // inverse extend-add maps of the children of large fronts (assembly by gather)
+    std::vector<int64_t> iptr(S.nsup, -1);
+    std::vector<int32_t> imap;
+    for (int64_t c = 0; c < S.nsup; c++) {
+      const int64_t par = S.sparent[c];
+      if (par < 0 || S.nf(par) <= kSmallMaxNf) continue;
+      const int64_t nuc = S.nf(c) - S.ns(c);
+      iptr[c] = (int64_t)imap.size();
+      imap.resize(imap.size() + S.nf(par), -1);
+      for (int64_t a = 0; a < nuc; a++) imap[iptr[c] + S.emap[S.eptr[c] + a]] = (int32_t)a;
+    }
+    P.d_iptr.upload(ctx, iptr);
+    P.d_imap.upload(ctx, imap);
+  }
   build_schedule(P);
   P.meta.sfirst = P.d_sfirst.get();
   P.meta.rptr = P.d_rptr.get();
@@ -250,6 +265,8 @@ void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const in
   P.meta.adst = P.d_adst.get();
   P.meta.tilew = P.d_tilew.get();
   P.meta.tptr = P.d_tptr.get();
+  P.meta.iptr = P.d_iptr.get();
+  P.meta.imap = P.d_imap.get();
   P.ws_batches = 0;
   P.scratch.reset(new NumFactor());
   factor_alloc(P, *P.scratch);

@@ -114,7 +114,8 @@ struct Pencil {
   // device metadata
   DBuf<int64_t> d_sfirst, d_rptr, d_lptr, d_uptr, d_wptr, d_tptr, d_eptr, d_cptr, d_acptr, d_asrc,
       d_adst, d_perm, d_pbase;
-  DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched;
+  DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched, d_imap;
+  DBuf<int64_t> d_iptr;
   FrontMeta meta{};
   std::vector<LevelPlan> levels;
   std::vector<int32_t> h_sched;   // host copy of the schedule array

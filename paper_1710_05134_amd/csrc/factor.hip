@@ -6,10 +6,13 @@
 //     assemble originals fma(-sigma, b, a), add children's update blocks, then
 //     unblocked Bunch-Kaufman over the fully-summed columns, write the panel,
 //     D and the update block.
-//   * larger fronts: k_front_init assembles column chunks in HBM; then per
-//     pivot tile of kNB columns: k_tile_factor (Bunch-Kaufman inside the tile, in
-//     LDS), k_panel_trsm (rows below the tile: L21 = S21 P^T L11^{-T} D^{-1} and
-//     W = L21 D), k_schur (trailing lower triangle -= W L21^T on FP64 MFMA).
+//   * larger fronts: k_front_init assembles column chunks in HBM (each entry
+//     written once: children's contributions gathered through inverse maps, then
+//     the original entries added); then per pivot tile of kNB columns:
+//     k_tile_factor (Bunch-Kaufman inside the tile, in LDS), k_panel_trsm (rows
+//     below the tile: L21 = S21 P^T L11^{-T} D^{-1} and W = L21 D), k_schur
+//     (trailing lower triangle -= W L21^T on FP64 MFMA).  The host runs the next
+//     tile's factorization on a second stream once its diagonal block is updated.
 // Row interchanges stay inside a tile; rows of earlier panels are not swapped --
 // the solve applies each tile's permutation when it reaches that tile.
 #include <hip/hip_runtime.h>
@@ -539,36 +542,49 @@ __global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* task
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
   const double sigma = *sigma_dev;
-  // a root's update block does not exist: its columns beyond ns never occur (nu == 0)
-  for (int j = c0 + wave; j < c1; j += NW)
-    for (int i = j + lane; i < f.nf; i += 64) *f.at(i, j) = 0.0;
+  // every entry (i >= j) of the chunk is written once: the sum of the children's
+  // update-block entries that map to it (through their inverse maps), children in
+  // list order; a root's update block does not exist (nu == 0, no columns >= ns)
+  const int64_t q0 = M.cptr[s], q1 = M.cptr[s + 1];
+  constexpr int RU = 8;   // row groups of 64 per lane and iteration: independent load chains
+  for (int j = c0 + wave; j < c1; j += NW) {
+    for (int i0 = j; i0 < f.nf; i0 += 64 * RU) {
+      T v[RU];
+#pragma unroll
+      for (int u = 0; u < RU; u++) v[u] = 0.0;
+      for (int64_t q = q0; q < q1; q++) {
+        const int c = M.clist[q];
+        const int32_t* inv = M.imap + M.iptr[c];
+        const int bj = inv[j];
+        if (bj < 0) continue;
+        const int nuc = (int)(M.rptr[c + 1] - M.rptr[c] - (M.sfirst[c + 1] - M.sfirst[c]));
+        const T* Uc = U + M.uptr[c] + (int64_t)bj * nuc;
+        int ai[RU];
+#pragma unroll
+        for (int u = 0; u < RU; u++) ai[u] = inv[min(i0 + 64 * u + lane, f.nf - 1)];
+        T uv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; u++) uv[u] = Uc[max(ai[u], 0)];   // clamped: a valid entry
+#pragma unroll
+        for (int u = 0; u < RU; u++)
+          if (ai[u] >= 0) v[u] += uv[u];
+      }
+#pragma unroll
+      for (int u = 0; u < RU; u++) {
+        const int i = i0 + 64 * u + lane;
+        if (i < f.nf) *f.at(i, j) = v[u];
+      }
+    }
+  }
   __syncthreads();
+  // original entries of A - sigma B (fully-summed columns only)
   if (c0 < f.ns) {
     const int64_t f0 = M.sfirst[s];
     const int64_t e1 = M.acptr[f0 + min(c1, f.ns)];
     for (int64_t e = M.acptr[f0 + c0] + tid; e < e1; e += NT) {
       const int64_t p = M.asrc[e];
-      f.Lp[M.adst[e]] = fma(-sigma, bval[p], aval[p]);
+      f.Lp[M.adst[e]] += fma(-sigma, bval[p], aval[p]);
     }
-  }
-  __syncthreads();
-  for (int64_t q = M.cptr[s]; q < M.cptr[s + 1]; q++) {
-    const int c = M.clist[q];
-    const int nuc = (int)(M.rptr[c + 1] - M.rptr[c] - (M.sfirst[c + 1] - M.sfirst[c]));
-    const T* Uc = U + M.uptr[c];
-    const int32_t* map = M.emap + M.eptr[c];
-    // child columns b whose parent column map[b] lies in [c0, c1)
-    int lo = 0, hi = nuc;
-    while (lo < hi) { int mid = (lo + hi) >> 1; if (map[mid] < c0) lo = mid + 1; else hi = mid; }
-    const int b0 = lo;
-    hi = nuc;
-    while (lo < hi) { int mid = (lo + hi) >> 1; if (map[mid] < c1) lo = mid + 1; else hi = mid; }
-    const int b1 = lo;
-    for (int b = b0 + wave; b < b1; b += NW) {
-      const int jc = map[b];
-      for (int a = b + lane; a < nuc; a += 64) *f.at(map[a], jc) += Uc[a + (int64_t)b * nuc];
-    }
-    __syncthreads();
   }
 }
 
