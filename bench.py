@@ -10,8 +10,9 @@ device before the timed region; the cold analysis time is reported apart.
 
 Printed: one JSON line with the step time (`value`, seconds, lower is better),
 the LDL^T GFLOP/s of one factorization at the first bisection shift, the
-roofline of the dominant kernel (FP64 MFMA Schur update) from HIP events around
-its launches, and the CPU oracle timed on a bounded sample of the same workload.
+roofline of the dominant kernel (k_gemm_lt, the FP64-MFMA left-looking and
+contribution-block products) from HIP events around its launches, and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -63,7 +64,7 @@ def cpu_baseline(pencil, sigma: float, n_factorizations: int, sample_flops: floa
 
 
 KERNEL_SOURCES = ("paper_1710_05134_amd/csrc/factor.hip", "paper_1710_05134_amd/csrc/device.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_schur_n524k_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_lt_n524k_traffic.md")
 PMC_SIGMA = -3.0
 COPY_DOUBLES = 2 ** 27          # calibration copy: 1 GiB read + 1 GiB written
 
@@ -77,8 +78,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def schur_traffic():
-    """HBM bytes per k_schur launch from the committed counter summary, or None if
+def gemm_traffic():
+    """HBM bytes per k_gemm_lt launch from the committed counter summary, or None if
     it is missing or was taken on other kernel sources."""
     try:
         kv = {}
@@ -88,7 +89,7 @@ def schur_traffic():
                 kv[k.strip("` ")] = v.strip().strip("`")
         if kv.get("kernel_source_sha256") != kernel_source_hash():
             return None
-        return float(kv["k_schur_hbm_bytes_per_launch"])
+        return float(kv["k_gemm_lt_hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -165,12 +166,12 @@ def summarize(stats_csv, fetch_csv, write_csv, command, pmc_command):
             short = nm.replace("void kth::(anonymous namespace)::", "").split("(")[0]
             out.append(f"| `{short}` | {fe[nm][1]} | {rf / 1e9:.4f} | {rw / 1e9:.4f} | "
                        f"{(rf + rw) * fe[nm][1] / 1e9:.2f} |")
-        sch = [nm for nm in keys if "k_schur<256, double>" in nm or "k_schur<256>" in nm]
+        sch = [nm for nm in keys if "k_gemm_lt<256, double>" in nm]
         if sch:
             nm = sch[0]
             per = fe[nm][0] * f_fac / fe[nm][1] + wr[nm][0] * w_fac / wr[nm][1]
-            out += ["", f"- k_schur_hbm_bytes_per_launch: {per:.6e}",
-                    f"- k_schur_launches: {fe[nm][1]}",
+            out += ["", f"- k_gemm_lt_hbm_bytes_per_launch: {per:.6e}",
+                    f"- k_gemm_lt_launches: {fe[nm][1]}",
                     f"- kernel_source_sha256: `{kernel_source_hash()}`"]
         out.append("")
     print("\n".join(out))
@@ -237,23 +238,24 @@ def main():
     sec = dt / args.steps
     info = infos[-1]
 
-    # LDL^T rate and the Schur-update roofline at the first bisection shift
+    # LDL^T rate and the roofline of the update products at the first bisection shift
     sigma2 = info["sigmas"][info["stage1_steps"]]
     profs = [P.profile_factor(sigma2) for _ in range(args.profile_reps)]
     tot = statistics.median(pr["total_s"] for pr in profs)
     ldlt_gflops = ana["flops"] / tot / 1e9
-    sch_s = statistics.median(pr["schur"]["seconds"] for pr in profs)
-    sch = profs[0]["schur"]
-    per_launch_flops = sch["flops"] / max(sch["launches"], 1)
-    # algorithmic bytes: each updated lower-triangle entry read and written once (16 B per
-    # 128 flops of a rank-64 update); the two 64-column panels are not counted
-    sch_bytes = sch["flops"] / 8.0
-    avg_launch_s = sch_s / max(sch["launches"], 1)
+    classes = ("small", "assemble", "tile", "trsm", "gemm", "reduce")
+    gm_s = statistics.median(pr["gemm"]["seconds"] for pr in profs)
+    gm = profs[0]["gemm"]
+    launches = max(gm["launches"], 1)
+    per_launch_flops = gm["flops"] / launches
+    per_launch_bytes = gm["bytes"] / launches
+    avg_launch_s = gm_s / launches
     achieved = per_launch_flops / avg_launch_s / 1e12
-    log(f"factorization {tot * 1e3:.1f} ms = {ldlt_gflops:.0f} GFLOP/s; schur {sch_s * 1e3:.1f} ms "
-        f"over {sch['launches']} launches = {achieved:.2f} TFLOP/s; classes "
+    log(f"factorization {tot * 1e3:.1f} ms = {ldlt_gflops:.0f} GFLOP/s; k_gemm_lt {gm_s * 1e3:.1f} ms "
+        f"over {gm['launches']} launches = {achieved:.2f} TFLOP/s, "
+        f"{gm['bytes'] / gm_s / 1e9:.0f} GB/s algorithmic; classes "
         + ", ".join(f"{k} {statistics.median(pr[k]['seconds'] for pr in profs) * 1e3:.1f} ms"
-                    for k in ("small", "assemble", "tile", "trsm", "schur")))
+                    for k in classes))
 
     out = {
         "metric": METRIC,
@@ -285,17 +287,19 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_schur (FP64 v_mfma_f64_16x16x4 rank-64 Schur update)",
+            "kernel": "k_gemm_lt (left-looking and contribution-block products, FP64 v_mfma_f64_16x16x4)",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": schur_traffic(),
+            "traffic": gemm_traffic(),
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes_per_launch": sch_bytes / max(sch["launches"], 1),
-            "launches": sch["launches"],
+            "algorithmic_bytes_per_launch": per_launch_bytes,
+            "algorithmic_gbs": per_launch_bytes / avg_launch_s / 1e9,
+            "launches": gm["launches"],
             "flops_per_launch": per_launch_flops,
             "avg_launch_us": avg_launch_s * 1e6,
+            "classes_ms": {k: statistics.median(pr[k]["seconds"] for pr in profs) * 1e3 for k in classes},
         },
     }
     if not args.no_cpu_baseline:

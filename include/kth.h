@@ -179,12 +179,15 @@ kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double
                             double* grad_a, double* grad_b);
 
 /* Measurement: one FP64 factorization of A - sigma B with a HIP event pair around
- * every kernel launch on the context stream.  out (nout >= 20 doubles) receives
+ * every kernel launch (on the context stream, or on the library's second stream
+ * for the pivot tiles factored ahead).  out (nout >= 28 doubles) receives
  *   [0] elapsed seconds (first to last event), [1] algorithmic flops of one
  *   factorization (exact structure), [2] the same over the padded fronts,
- *   [3 + 3c], [4 + 3c], [5 + 3c] for kernel class c = 0..4 (small fronts, large-front
- *   assembly, pivot tiles, panel solves, Schur updates): seconds, dense operation
- *   count of those launches, number of launches; [18] nu(sigma). */
+ *   [3 + 4c .. 6 + 4c] for kernel class c = 0..5 (small fronts, large-front
+ *   assembly, pivot tiles, panel solves, left-looking and contribution-block
+ *   products k_gemm_lt, split-depth reductions): seconds, dense operation count,
+ *   number of launches, algorithmic HBM bytes (class 4 only: each output entry read
+ *   and written once, each operand row read once); [27] nu(sigma). */
 kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t nout);
 
 /* Diagnostics: one v_mfma_f64_16x16x4 on device 0, zero accumulator; lane l of

@@ -207,12 +207,13 @@ class Pencil:
 
     def profile_factor(self, sigma: float) -> dict:
         """One factorization with per-kernel-class event timing (see kth.h)."""
-        out = np.zeros(20)
-        _check(lib().kth_profile_factor(self.h, float(sigma), _p(out, C.c_double), 20), self.ctx.h)
-        names = ("small", "assemble", "tile", "trsm", "schur")
-        d = dict(total_s=out[0], flops=out[1], flops_padded=out[2], nu=int(out[18]))
+        out = np.zeros(28)
+        _check(lib().kth_profile_factor(self.h, float(sigma), _p(out, C.c_double), 28), self.ctx.h)
+        names = ("small", "assemble", "tile", "trsm", "gemm", "reduce")
+        d = dict(total_s=out[0], flops=out[1], flops_padded=out[2], nu=int(out[27]))
         for c, nm in enumerate(names):
-            d[nm] = dict(seconds=out[3 + 3 * c], flops=out[4 + 3 * c], launches=int(out[5 + 3 * c]))
+            d[nm] = dict(seconds=out[3 + 4 * c], flops=out[4 + 4 * c], launches=int(out[5 + 4 * c]),
+                         bytes=out[6 + 4 * c])
         return d
 
     def factor(self, sigma: float, precision: int = KTH_FP64) -> "Factor":

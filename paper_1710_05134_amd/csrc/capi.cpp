@@ -350,7 +350,7 @@ kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double
 }
 
 kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t nout) {
-  if (!p || !out || nout < 20) return KTH_EINVAL;
+  if (!p || !out || nout < 28) return KTH_EINVAL;
   return guarded(&p->ctx->c, [&] {
     set_device(p->ctx->c);
     FactorProfile prof;
@@ -363,11 +363,12 @@ kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t n
     out[1] = p->p.S.flops;
     out[2] = p->p.S.flops_padded;
     for (int c = 0; c < PROF_NCLASS; c++) {
-      out[3 + 3 * c] = prof.time[c];
-      out[4 + 3 * c] = prof.flops[c];
-      out[5 + 3 * c] = (double)prof.launches[c];
+      out[3 + 4 * c] = prof.time[c];
+      out[4 + 4 * c] = prof.flops[c];
+      out[5 + 4 * c] = (double)prof.launches[c];
+      out[6 + 4 * c] = prof.bytes[c];
     }
-    out[18] = (double)F.hs.neg;
+    out[27] = (double)F.hs.neg;
   });
 }
 

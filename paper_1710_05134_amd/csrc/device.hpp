@@ -13,7 +13,6 @@ struct FrontMeta {
   const int32_t* rows;    // front row lists (elimination indices)
   const int64_t* lptr;    // [nsup+1] panel offsets (nf*ns, ld nf)
   const int64_t* uptr;    // [nsup]   update-block offsets in the pool (-1: none)
-  const int64_t* wptr;    // [nsup]   panel-workspace offsets (nf*NB, ld nf; -1: small front)
   const int64_t* eptr;    // [nsup+1] extend-add map offsets
   const int32_t* emap;
   const int64_t* cptr;    // [nsup+1] children
@@ -49,6 +48,8 @@ constexpr int kSolveChunk = 256;
 constexpr int kSolveRows = 256;
 // Schur-update output tile.
 constexpr int kTile = 64;
+// depth segment of a split left-looking update
+constexpr int kSegK = 256;
 
 struct Int2 { int32_t a, b; };
 
@@ -61,6 +62,7 @@ struct Batch {
   int64_t sU = 0;   // update-block pool
   int64_t sW = 0;   // panel workspace
   int64_t sT = 0;   // tile inverses
+  int64_t sP = 0;   // split-depth partial products
   int64_t sN = 0;   // n-vectors (D, E, pivot order)
   const double* sig = nullptr;   // [batch] shifts
 };
@@ -85,12 +87,20 @@ template <typename T>
 void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t,
                        const Batch& bt, int nb, T* L, T* W, const double* D, const double* E,
                        const int32_t* tperm, const T* tinv, FactStats* st, hipStream_t s);
+// Left-looking updates C -= L W^T (W = L D panel-shaped): mode 0/1, column block of
+// pivot tile t for tasks (front, first row) -- mode 0 the tile's diagonal block,
+// mode 1 rows below it; mode 2, tasks (front, lower tile number) of the
+// contribution block with depth ns.
+// Modes 0 / 1 with nseg > 1 split the depth into segments of kSegK whose partial
+// products go to part (bt.sP elements per batch: count * nseg * kTile^2 needed);
+// launch_gemm_reduce then applies them.
 template <typename T>
-// mode 0: every tile of the trailing lower triangles; 1: only the diagonal block of
-// each front's next pivot tile (grid = nfronts); 2: all but that block.
-void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
-                  int32_t nfronts, int32_t ntiles, int32_t t, int mode, const Batch& bt, int nb,
-                  T* L, T* U, const T* W, hipStream_t s);
+void launch_gemm_lt(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int mode,
+                    int nseg, const Batch& bt, int nb, T* L, T* U, const T* W, T* part,
+                    hipStream_t s);
+template <typename T>
+void launch_gemm_reduce(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int nseg,
+                        const Batch& bt, int nb, T* L, const T* part, hipStream_t s);
 void launch_set_scalar(double* p, double v, hipStream_t s);
 void launch_set_scalars(double* p, int n, const double* values, hipStream_t s);
 // MFMA operand-layout probe (tests only): D = A(16x4) * B(4x16) via one instruction.

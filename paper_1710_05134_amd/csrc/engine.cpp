@@ -64,9 +64,10 @@ static void build_schedule(Pencil& P) {
   auto align2 = [&]() { if (sched.size() & 1) sched.push_back(0); };
   std::vector<std::vector<int32_t>> bylevel(S.nlevels);
   for (int64_t s = 0; s < S.nsup; s++) bylevel[S.level[s]].push_back((int32_t)s);
-  std::vector<int64_t> wptr(S.nsup, -1), tptr(S.nsup, -1);
+  std::vector<int64_t> tptr(S.nsup, -1);
   std::vector<int32_t> tilew(S.nsup, 0);
-  P.wsize = 1;
+  P.wsize = std::max<int64_t>(1, S.lptr[S.nsup]);   // W = L D, panel-shaped
+  P.psize = 1;
   P.tsize = 1;
   P.splan.partial_size = 1;
   P.levels.assign(S.nlevels, LevelPlan());
@@ -84,16 +85,13 @@ static void build_schedule(Pencil& P) {
     std::stable_sort(large.begin(), large.end(), [&](int32_t a, int32_t b) { return S.ns(a) > S.ns(b); });
     lp.large_off = (int32_t)sched.size();
     lp.large_cnt = (int32_t)large.size();
-    int64_t woff = 0, toff = 0;
+    int64_t toff = 0;
     for (int32_t s : large) {
       sched.push_back(s);
       tilew[s] = kNB;
-      wptr[s] = woff;
-      woff += S.nf(s) * kNB;
       tptr[s] = toff;
       toff += kNB * kNB;
     }
-    P.wsize = std::max(P.wsize, woff);
     P.tsize = std::max(P.tsize, toff);
     align2();
     lp.init_off = (int32_t)sched.size();
@@ -119,25 +117,34 @@ static void build_schedule(Pencil& P) {
         tpre.push_back((int32_t)((sched.size() - sp.trsm_off) / 2));
       }
       sp.trsm_cnt = (int32_t)((sched.size() - sp.trsm_off) / 2);
-      sp.trsm_prefix_off = (int32_t)sched.size();
-      sched.insert(sched.end(), tpre.begin(), tpre.end());
-      sp.prefix_off = (int32_t)sched.size();
-      int64_t tot = 0;
-      for (int32_t q = 0; q < act; q++) {
-        sched.push_back((int32_t)tot);
-        int32_t s = large[q];
-        int64_t ns = S.ns(s), nf = S.nf(s);
-        int64_t k0 = t * kNB, kb = std::min<int64_t>(kNB, ns - k0), r0 = k0 + kb;
-        int64_t nc1 = r0 < ns ? (ns - r0 + kTile - 1) / kTile : 0;
-        int64_t nc2 = (nf - ns + kTile - 1) / kTile;
-        int64_t T = nc1 + nc2;
-        tot += T * (T + 1) / 2;
-      }
-      sched.push_back((int32_t)tot);
-      if (tot > INT32_MAX) throw Error(KTH_EINVAL, "front too large for the tile schedule");
-      sp.ntiles = (int32_t)tot;
+      // left-looking update of this tile's column block (steps after the first):
+      // its diagonal block, then rows below it in kTile chunks
+      sp.ll_diag_off = (int32_t)sched.size();
+      if (t > 0)
+        for (int32_t q = 0; q < act; q++) { sched.push_back(large[q]); sched.push_back((int32_t)(t * kNB)); }
+      sp.ll_diag_cnt = (int32_t)((sched.size() - sp.ll_diag_off) / 2);
+      sp.ll_rest_off = (int32_t)sched.size();
+      if (t > 0)
+        for (int32_t q = 0; q < act; q++) {
+          const int32_t s = large[q];
+          for (int64_t r = t * kNB + kTile; r < S.nf(s); r += kTile) { sched.push_back(s); sched.push_back((int32_t)r); }
+        }
+      sp.ll_rest_cnt = (int32_t)((sched.size() - sp.ll_rest_off) / 2);
+      sp.ll_nseg = std::max<int32_t>(1, (int32_t)((t * kNB + kSegK - 1) / kSegK));
+      if (sp.ll_nseg > 1)
+        P.psize = std::max<int64_t>(P.psize, (int64_t)std::max(sp.ll_diag_cnt, sp.ll_rest_cnt) *
+                                                 sp.ll_nseg * kTile * kTile);
       lp.steps.push_back(sp);
     }
+    // contribution blocks: lower kTile x kTile tiles of each nu x nu block (depth ns)
+    align2();
+    lp.cb_off = (int32_t)sched.size();
+    for (int32_t s : large) {
+      const int64_t nu = S.nf(s) - S.ns(s), T = (nu + kTile - 1) / kTile;
+      if (T * (T + 1) / 2 > INT32_MAX) throw Error(KTH_EINVAL, "front too large for the tile schedule");
+      for (int64_t tl = 0; tl < T * (T + 1) / 2; tl++) { sched.push_back(s); sched.push_back((int32_t)tl); }
+    }
+    lp.cb_cnt = (int32_t)((sched.size() - lp.cb_off) / 2);
   }
   std::vector<int64_t> pbase(S.nsup, -1);
   P.splan.partial_half = 0;
@@ -188,7 +195,6 @@ static void build_schedule(Pencil& P) {
   Ctx* c = P.ctx;
   P.d_sched.upload(c, sched);
   P.h_sched = sched;
-  P.d_wptr.upload(c, wptr);
   P.d_tptr.upload(c, tptr);
   P.d_tilew.upload(c, tilew);
   P.d_pbase.upload(c, pbase);
@@ -255,7 +261,6 @@ void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const in
   P.meta.rows = P.d_rows.get();
   P.meta.lptr = P.d_lptr.get();
   P.meta.uptr = P.d_uptr.get();
-  P.meta.wptr = P.d_wptr.get();
   P.meta.eptr = P.d_eptr.get();
   P.meta.emap = P.d_emap.get();
   P.meta.cptr = P.d_cptr.get();
@@ -297,6 +302,7 @@ static void ensure_workspace(Pencil& P, int nb) {
   P.U.alloc(c, (size_t)P.S.pool_size * nb);
   P.W.alloc(c, (size_t)P.wsize * nb);
   P.Tinv.alloc(c, (size_t)std::max<int64_t>(P.tsize, 1) * nb);
+  P.Part.alloc(c, (size_t)P.psize * nb);
   P.ws_batches = nb;
 }
 
@@ -320,9 +326,10 @@ int factor_batch_capacity(Pencil& P, int cap) {
   size_t fr = 0, tot = 0;
   KTH_HIP(hipMemGetInfo(&fr, &tot));
   const double per = 8.0 * ((double)P.S.lptr[P.S.nsup] + (double)P.S.pool_size + (double)P.wsize +
-                            (double)P.tsize + 3.0 * (double)P.n);
+                            (double)P.tsize + (double)P.psize + 3.0 * (double)P.n);
   // already-held workspace counts as available for the batch it serves
-  const double have = 8.0 * ((double)P.S.pool_size + (double)P.wsize + (double)P.tsize) * P.ws_batches;
+  const double have =
+      8.0 * ((double)P.S.pool_size + (double)P.wsize + (double)P.tsize + (double)P.psize) * P.ws_batches;
   int k = (int)((0.8 * (double)fr + have) / per);
   return std::max(1, std::min(k, std::min(cap, kMaxBatch)));
 }
@@ -336,7 +343,8 @@ struct ProfScope {
   FactorProfile* p;
   hipStream_t st;
   int cls;
-  ProfScope(FactorProfile* pr, hipStream_t s, int c, double flops) : p(pr), st(s), cls(c) {
+  ProfScope(FactorProfile* pr, hipStream_t s, int c, double flops, double bytes = 0.0)
+      : p(pr), st(s), cls(c) {
     if (!p) return;
     hipEvent_t e;
     KTH_HIP(hipEventCreate(&e));
@@ -344,6 +352,7 @@ struct ProfScope {
     p->ev.push_back(e);
     p->cls.push_back(c);
     p->flops[c] += flops;
+    p->bytes[c] += bytes;
     p->launches[c]++;
   }
   ~ProfScope() {
@@ -382,6 +391,7 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
   bt.sU = P.S.pool_size;
   bt.sW = P.wsize;
   bt.sT = std::max<int64_t>(P.tsize, 1);
+  bt.sP = P.psize;
   bt.sN = P.n;
   bt.sig = F.sig.get();
   const int32_t* sched = P.d_sched.get();
@@ -390,6 +400,7 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
   T* Uf = reinterpret_cast<T*>(P.U.get());
   T* Wf = reinterpret_cast<T*>(P.W.get());
   T* Tf = reinterpret_cast<T*>(P.Tinv.get());
+  T* Pf = reinterpret_cast<T*>(P.Part.get());
   const std::vector<int32_t>& hs = P.h_sched;
   for (const LevelPlan& lp : P.levels) {
     if (lp.small_cnt > 0) {
@@ -410,26 +421,37 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
       launch_front_init(P.meta, reinterpret_cast<const Int2*>(sched + lp.init_off), lp.init_cnt, av,
                         bv, bt, nb, Lf, Uf, st);
     }
-    // Look-ahead: after the panel solve of step q, the diagonal block of each front's
-    // next pivot tile is updated first; the next tile is then factored on the
-    // auxiliary stream while the rest of the Schur update runs on the context stream.
-    auto step_flops = [&](const StepPlan& sp, double& fl_tile, double& fl_trsm, double& fl_schur) {
-      fl_tile = fl_trsm = fl_schur = 0;
-      if (!prof) return;
+    // Left-looking steps with look-ahead: after the panel solve of step q, the
+    // column block of tile q+1 is brought up to date (its diagonal block first);
+    // tile q+1 is factored on the auxiliary stream while the rows below it are
+    // updated on the context stream.  Contribution blocks follow the last step.
+    // per step: operation counts and, for the column-block update, its algorithmic
+    // bytes (each C entry read and written once, the depth-k0 rows of L below and
+    // of W in the tile read once; diagonal-block counts are kept apart)
+    struct StepCost { double tile = 0, trsm = 0, ll = 0, ll_bytes = 0, lld = 0, lld_bytes = 0; };
+    auto step_cost = [&](const StepPlan& sp) {
+      StepCost c;
+      if (!prof) return c;
       for (int32_t q = 0; q < sp.nfronts; q++) {
         const int32_t s = hs[lp.large_off + q];
         const double ns = (double)S.ns(s), nf = (double)S.nf(s);
         const double k0 = (double)sp.t * kNB, kb = std::min<double>(kNB, ns - k0);
         const double R = nf - k0 - kb;   // rows below the tile
-        for (int64_t j = 0; j < (int64_t)kb; j++) { double cc = kb - 1 - j; fl_tile += cc * cc + 2 * cc; }
-        fl_trsm += R * (kb * kb + kb);      // R rows: triangular solve + diagonal scaling
-        fl_schur += kb * R * (R + 1);       // rank-kb update of the R x R lower triangle
+        for (int64_t j = 0; j < (int64_t)kb; j++) { double cc = kb - 1 - j; c.tile += cc * cc + 2 * cc; }
+        c.trsm += R * (kb * kb + kb);      // R rows: triangular solve + diagonal scaling
+        const double rd = std::min<double>(kTile, nf - k0);   // rows of the diagonal task
+        const double ed = kb * rd - kb * (kb - 1) / 2, er = kb * (nf - k0 - rd);
+        c.lld += 2.0 * k0 * ed;
+        c.ll += 2.0 * k0 * er;
+        c.lld_bytes += 16.0 * ed + 8.0 * k0 * (rd + kb);
+        c.ll_bytes += 16.0 * er + 8.0 * k0 * ((nf - k0 - rd) + kb);
       }
+      return c;
     };
     for (size_t q = 0; q < lp.steps.size(); q++) {
       const StepPlan& sp = lp.steps[q];
-      double fl_tile, fl_trsm, fl_schur;
-      step_flops(sp, fl_tile, fl_trsm, fl_schur);
+      const StepCost cs = step_cost(sp);
+      const double fl_tile = cs.tile, fl_trsm = cs.trsm;
       if (q == 0) {
         ProfScope ps(prof, st, PROF_TILE, fl_tile);
         launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, bt, nb, Lf,
@@ -445,31 +467,47 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
       }
       if (q + 1 < lp.steps.size()) {
         const StepPlan& nx = lp.steps[q + 1];
-        double nt_tile, nt_trsm, nt_schur;
-        step_flops(nx, nt_tile, nt_trsm, nt_schur);
+        const StepCost cn = step_cost(nx);
+        const Int2* dtask = reinterpret_cast<const Int2*>(sched + nx.ll_diag_off);
+        const Int2* rtask = reinterpret_cast<const Int2*>(sched + nx.ll_rest_off);
         {
-          ProfScope ps(prof, st, PROF_SCHUR, 0.0);
-          launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
-                       sp.t, 1, bt, nb, Lf, Uf, Wf, st);
+          ProfScope ps(prof, st, PROF_GEMM, cn.lld, cn.lld_bytes);
+          launch_gemm_lt(P.meta, dtask, nx.ll_diag_cnt, nx.t, 0, nx.ll_nseg, bt, nb, Lf, Uf, Wf, Pf, st);
+        }
+        if (nx.ll_nseg > 1) {
+          ProfScope ps(prof, st, PROF_REDUCE, 0.0);
+          launch_gemm_reduce(P.meta, dtask, nx.ll_diag_cnt, nx.t, nx.ll_nseg, bt, nb, Lf, Pf, st);
         }
         KTH_HIP(hipEventRecord(c->ev_diag, st));
         KTH_HIP(hipStreamWaitEvent(c->aux, c->ev_diag, 0));
         {
-          ProfScope ps(prof, c->aux, PROF_TILE, nt_tile);
+          ProfScope ps(prof, c->aux, PROF_TILE, cn.tile);
           launch_tile_factor(P.meta, sched + lp.large_off, nx.nfronts, nx.t, bt, nb, Lf,
                              F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), c->aux);
         }
         KTH_HIP(hipEventRecord(c->ev_tile, c->aux));
         {
-          ProfScope ps(prof, st, PROF_SCHUR, fl_schur);
-          launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
-                       sp.t, 2, bt, nb, Lf, Uf, Wf, st);
+          ProfScope ps(prof, st, PROF_GEMM, cn.ll, cn.ll_bytes);
+          launch_gemm_lt(P.meta, rtask, nx.ll_rest_cnt, nx.t, 1, nx.ll_nseg, bt, nb, Lf, Uf, Wf, Pf, st);
         }
-      } else {
-        ProfScope ps(prof, st, PROF_SCHUR, fl_schur);
-        launch_schur(P.meta, sched + lp.large_off, sched + sp.prefix_off, sp.nfronts, sp.ntiles,
-                     sp.t, 0, bt, nb, Lf, Uf, Wf, st);
+        if (nx.ll_nseg > 1 && nx.ll_rest_cnt > 0) {
+          ProfScope ps(prof, st, PROF_REDUCE, 0.0);
+          launch_gemm_reduce(P.meta, rtask, nx.ll_rest_cnt, nx.t, nx.ll_nseg, bt, nb, Lf, Pf, st);
+        }
       }
+    }
+    if (lp.cb_cnt > 0) {
+      double fl_cb = 0, by_cb = 0;
+      if (prof)
+        for (int32_t q = 0; q < lp.large_cnt; q++) {
+          const int32_t s = hs[lp.large_off + q];
+          const double ns = (double)S.ns(s), nu = (double)(S.nf(s) - S.ns(s));
+          fl_cb += 2.0 * ns * nu * (nu + 1) / 2;
+          by_cb += 16.0 * nu * (nu + 1) / 2 + 2.0 * 8.0 * ns * nu;   // C once; L_u and W_u once
+        }
+      ProfScope ps(prof, st, PROF_GEMM, fl_cb, by_cb);
+      launch_gemm_lt(P.meta, reinterpret_cast<const Int2*>(sched + lp.cb_off), lp.cb_cnt, 0, 2, 1, bt,
+                     nb, Lf, Uf, Wf, Pf, st);
     }
   }
   KTH_HIP(hipGetLastError());

@@ -86,15 +86,17 @@ struct DBuf {
 struct StepPlan {
   int32_t t;
   int32_t nfronts;     // active large fronts (prefix of the level's sorted list)
-  int32_t trsm_off, trsm_cnt;   // Int2 tasks (offset in int32 units)
-  int32_t trsm_prefix_off;      // [nfronts+1] task ranges per active front
-  int32_t prefix_off, ntiles;   // tile prefix over active fronts
+  int32_t trsm_off, trsm_cnt;        // Int2 (front, row) panel-solve tasks (offset in int32 units)
+  int32_t ll_diag_off, ll_diag_cnt;  // Int2 (front, k0): the tile's diagonal block (t > 0)
+  int32_t ll_rest_off, ll_rest_cnt;  // Int2 (front, row): rows below it (t > 0)
+  int32_t ll_nseg;                   // depth segments of those updates (depth t * kNB)
 };
 
 struct LevelPlan {
   int32_t small_off = 0, small_cnt = 0, small_maxnf = 0;
   int32_t init_off = 0, init_cnt = 0;
   int32_t large_off = 0, large_cnt = 0;
+  int32_t cb_off = 0, cb_cnt = 0;    // Int2 (front, lower tile) of the contribution blocks
   std::vector<StepPlan> steps;
 };
 
@@ -112,7 +114,7 @@ struct Pencil {
   DBuf<int32_t> col;
   DBuf<double> aval, bval, zeros;
   // device metadata
-  DBuf<int64_t> d_sfirst, d_rptr, d_lptr, d_uptr, d_wptr, d_tptr, d_eptr, d_cptr, d_acptr, d_asrc,
+  DBuf<int64_t> d_sfirst, d_rptr, d_lptr, d_uptr, d_tptr, d_eptr, d_cptr, d_acptr, d_asrc,
       d_adst, d_perm, d_pbase;
   DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched, d_imap;
   DBuf<int64_t> d_iptr;
@@ -120,11 +122,13 @@ struct Pencil {
   std::vector<LevelPlan> levels;
   std::vector<int32_t> h_sched;   // host copy of the schedule array
   SolvePlan splan;
-  int64_t wsize = 0;   // workspace doubles per factorization
+  int64_t wsize = 0;   // W = L D workspace (panel-shaped) elements per factorization
   int64_t tsize = 0;   // tile-inverse doubles per factorization
+  int64_t psize = 0;   // split-depth partial products per factorization
   int ws_batches = 0;  // factorizations the workspace below holds
-  DBuf<double> U, W;   // update-block pool, panel workspace (ws_batches copies)
+  DBuf<double> U, W;   // update-block pool, W = L D panels (ws_batches copies)
   DBuf<double> Tinv;   // inverses of the current pivot tiles (ws_batches copies)
+  DBuf<double> Part;   // partial products of split column-block updates (ws_batches copies)
   std::unique_ptr<NumFactor> scratch;   // factor reused by inertia-only calls
   std::unique_ptr<NumFactor> batchF;    // batched inertia-only factorizations (multisection)
   double flops() const { return S.flops; }
@@ -149,12 +153,13 @@ struct NumFactor {
 };
 
 // Per-kernel-class timing of one factorization (HIP events on the context stream).
-enum { PROF_SMALL = 0, PROF_INIT, PROF_TILE, PROF_TRSM, PROF_SCHUR, PROF_NCLASS };
+enum { PROF_SMALL = 0, PROF_INIT, PROF_TILE, PROF_TRSM, PROF_GEMM, PROF_REDUCE, PROF_NCLASS };
 struct FactorProfile {
   std::vector<hipEvent_t> ev;       // pairs (start, stop)
   std::vector<int> cls;             // class of each pair
   double time[PROF_NCLASS] = {0};   // seconds
   double flops[PROF_NCLASS] = {0};  // dense-front operation counts of the launches
+  double bytes[PROF_NCLASS] = {0};  // algorithmic HBM bytes of the launches (where stated)
   int64_t launches[PROF_NCLASS] = {0};
   double total = 0;                 // seconds, first to last event
   ~FactorProfile();

@@ -10,9 +10,12 @@
 //     written once: children's contributions gathered through inverse maps, then
 //     the original entries added); then per pivot tile of kNB columns:
 //     k_tile_factor (Bunch-Kaufman inside the tile, in LDS), k_panel_trsm (rows
-//     below the tile: L21 = S21 P^T L11^{-T} D^{-1} and W = L21 D), k_schur
-//     (trailing lower triangle -= W L21^T on FP64 MFMA).  The host runs the next
-//     tile's factorization on a second stream once its diagonal block is updated.
+//     below the tile: L21 = S21 P^T L11^{-T} D^{-1}, and W = L21 D kept
+//     panel-shaped); the column block of each tile is first brought up to date
+//     left-looking, C -= L(:, <k0) W(tile rows, <k0)^T on FP64 MFMA (k_gemm_lt),
+//     and once all tiles are done the contribution block receives
+//     -L_u W_u^T with depth ns in one product.  The host runs the next tile's
+//     factorization on a second stream once its diagonal block is updated.
 // Row interchanges stay inside a tile; rows of earlier panels are not swapped --
 // the solve applies each tile's permutation when it reaches that tile.
 #include <hip/hip_runtime.h>
@@ -718,7 +721,7 @@ template <> struct MF<float> {
 // Large fronts: rows below pivot tile t, 64 rows per workgroup.
 //   W = S P^T L_tt^{-T}  (MFMA, with the tile inverse from k_tile_factor)
 //   L21 = W D^{-1}       (1x1 / 2x2 blocks)
-// The panel rows receive L21, the workspace receives W (= L21 D).
+// The panel rows receive L21, the W panel (same layout) receives W (= L21 D).
 // ---------------------------------------------------------------------------
 template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* tasks, int t,
@@ -747,7 +750,7 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
   const int k0 = t * kNB;
   const int kb = min(kNB, ns - k0);
   T* Lp = L + M.lptr[s];
-  T* Wp = W + M.wptr[s];
+  T* Wp = W + M.lptr[s];   // W = L D, panel-shaped
   const T* Ti = tinv + M.tptr[s];
   for (int q = tid; q < kNB; q += NT) {
     dd[q] = q < kb ? D[f0 + k0 + q] : 1.0;
@@ -818,7 +821,7 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
       l = dd[q] != 0.0 ? wq / dd[q] : 0.0;
     }
     Lp[(r0 + r) + (int64_t)(k0 + q) * nf] = l;
-    Wp[(r0 + r) + (int64_t)q * nf] = wq;
+    Wp[(r0 + r) + (int64_t)(k0 + q) * nf] = wq;
     maxl = fmax(maxl, fabs((double)l));
   }
   maxl = block_max<NT>(maxl, sv);
@@ -826,117 +829,138 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
 }
 
 // ---------------------------------------------------------------------------
-// Large fronts: trailing update after tile t on FP64 MFMA (v_mfma_f64_16x16x4).
-// The trailing range [r0, nf) is cut into 64-chunks aligned at ns (so no chunk
-// mixes panel and update-block columns); one workgroup per lower tile (bi >= bj).
+// Large fronts: left-looking updates on FP64 MFMA (v_mfma_f64_16x16x4), C -= A B^T
+//   mode 0 / 1, column block of pivot tile t, rows [i0, i0 + kTile) (mode 0: the
+//     tile's own diagonal block, lower part; mode 1: rows below it):
+//       C(i, j) -= sum_{q < k0} L(i, q) W(j, q),   j in [k0, k0 + kb)
+//   mode 2, the contribution block, lower 64 x 64 tile number b of it:
+//       U(i, j) -= sum_{q < ns} L(ns + i, q) W(ns + j, q),   i >= j
+// W = L D is kept panel-shaped (same offsets and ld as L) by k_panel_trsm.  The
+// depth is walked in chunks of kNB columns staged through LDS; the next chunk's
+// loads are in flight while the current one feeds the matrix cores.
 // ---------------------------------------------------------------------------
-__device__ inline void chunk_range(int c, int r0, int ns, int nf, int nc1, int& b, int& e) {
-  if (c < nc1) { b = r0 + c * kTile; e = min(b + kTile, ns); }
-  else { b = ns + (c - nc1) * kTile; e = min(b + kTile, nf); }
-}
-
+// Split depth (modes 0 / 1, nseg > 1): workgroup g takes output tile g / nseg and
+// the depth segment [seg * kSegK, (seg + 1) * kSegK) with seg = g % nseg, and
+// stores its product in part[g] (kTile x kTile); k_gemm_reduce adds the segments
+// in order and applies them.
 template <int NT, typename T>
-__global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts,
-                                              const int32_t* tile_prefix, int nfronts, int t,
-                                              int mode, Batch bt, T* L, T* U, const T* W) {
+__global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, int t, int mode,
+                                                int nseg, Batch bt, T* L, T* U, const T* W,
+                                                T* part) {
   {
     const int64_t bidx = blockIdx.y;
     L += bidx * bt.sL; U += bidx * bt.sU; W += bidx * bt.sW;
+    part += bidx * bt.sP;
   }
-  __shared__ T As[kTile * kNB];  // W rows (i) x k, ld kTile
-  __shared__ T Bs[kTile * kNB];  // L rows (j) x k, ld kTile
-  // locate the front of this tile (mode 1: one workgroup per front, its tile 0)
+  __shared__ T As[kTile * kNB];  // A rows (i) x q, ld kTile
+  __shared__ T Bs[kTile * kNB];  // B rows (j) x q, ld kTile
   const int g = blockIdx.x;
-  int lo = 0, hi = nfronts - 1;
-  if (mode == 1) {
-    lo = g;
-  } else {
-    while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (tile_prefix[mid] <= g) lo = mid; else hi = mid - 1; }
-  }
-  const int s = fronts[lo];
-  const int tl = mode == 1 ? 0 : g - tile_prefix[lo];
+  const int seg = g % nseg;
+  const Int2 tk = tasks[g / nseg];
+  const int s = tk.a;
   const FrontRef<T> f = front_ref<T>(M, s, L, U);
-  const int k0 = t * kNB;
-  const int kb = min(kNB, f.ns - k0);
-  const int r0 = k0 + kb;
-  const int nc1 = r0 < f.ns ? (f.ns - r0 + kTile - 1) / kTile : 0;
-  // tile 0 of a front with a next pivot tile is that tile's diagonal block:
-  // mode 1 updates only it, mode 2 everything else, mode 0 all
-  if (mode == 1 && nc1 == 0) return;
-  if (mode == 2 && tl == 0 && nc1 > 0) return;
-  // tile index -> (bi, bj), bi >= bj
-  int bi = (int)((sqrt(8.0 * tl + 1.0) - 1.0) * 0.5);
-  while ((bi + 1) * (bi + 2) / 2 <= tl) bi++;
-  while (bi * (bi + 1) / 2 > tl) bi--;
-  const int bj = tl - bi * (bi + 1) / 2;
-  int ib, ie, jb, je;
-  chunk_range(bi, r0, f.ns, f.nf, nc1, ib, ie);
-  chunk_range(bj, r0, f.ns, f.nf, nc1, jb, je);
   const T* Lp = f.Lp;
-  const T* Wp = W + M.wptr[s];
+  const T* Wp = W + M.lptr[s];
+  int ia, ie, ja, je, K;   // C rows [ia, ie), columns [ja, je) (front numbering), depth K
+  bool tri;                // lower triangle only
+  T* Cb;                   // C(i, j) at Cb[(i - ia) + (j - ja) * ldc]
+  int64_t ldc;
+  int Kb = 0;              // first depth column of this workgroup
+  if (mode < 2) {
+    const int k0 = t * kNB, kb = min(kNB, f.ns - k0);
+    ia = tk.b; ie = min(ia + kTile, f.nf); ja = k0; je = k0 + kb; K = k0;
+    if (nseg > 1) { Kb = seg * kSegK; K = min(K, Kb + kSegK); }
+    tri = (ia == k0);
+    Cb = f.Lp + ia + (int64_t)ja * f.nf; ldc = f.nf;
+  } else {
+    const int tl = tk.b;
+    int bi = (int)((sqrt(8.0 * tl + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= tl) bi++;
+    while (bi * (bi + 1) / 2 > tl) bi--;
+    const int bj = tl - bi * (bi + 1) / 2;
+    ia = f.ns + bi * kTile; ie = min(ia + kTile, f.nf);
+    ja = f.ns + bj * kTile; je = min(ja + kTile, f.nf);
+    K = f.ns; tri = (bi == bj);
+    Cb = f.Ub + (ia - f.ns) + (int64_t)(ja - f.ns) * f.nu; ldc = f.nu;
+  }
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  // wave's 32x32 sub-tile: rows (i) wr.., columns (j) wc..
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  // C tile base: chunks never straddle ns, so the tile lies in the panel or in the update block
-  T* Cb;
-  int64_t ldc;
-  if (jb < f.ns) { Cb = f.Lp + ib + (int64_t)jb * f.nf; ldc = f.nf; }
-  else { Cb = f.Ub + (ib - f.ns) + (int64_t)(jb - f.ns) * f.nu; ldc = f.nu; }
-  // Output layout with A = L rows (j) and B = W rows (i): lane l holds i = l % 16 of
-  // its block and j = 4 r + l / 16 for register r -> 16 consecutive rows per column.
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // the wave's 32 x 32 sub-tile
+  // Output layout with A = rows i and B = rows j: lane l holds i = l % 16 of its
+  // block and j = mrow(r, l) for register r -> 16 consecutive rows per column.
   const int il = lane & 15;
-  const bool diag = (bi == bj);
-  // prefetch the C entries this thread will update (overlaps the operand staging)
-  T cv[2][2][4];
+  T cv[2][2][4];   // C entries of this thread, loaded during the last depth chunk
+  auto load_c = [&]() {
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+    for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++)
+      for (int b = 0; b < 2; b++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
-        const bool ok = (ib + i < ie) && (jb + j < je) && (!diag || i >= j);
-        cv[a][b][r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
-      }
-  {
-    constexpr int U = kTile * kNB / NT;   // 16 loads of each operand per thread, all in flight
-    T va[U], vb[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int x = u * NT + tid;
-      const int r = x % kTile, q = x / kTile;
-      const bool qok = q < kb;
-      va[u] = (qok && ib + r < ie) ? Wp[(ib + r) + (int64_t)q * f.nf] : 0.0;
-      vb[u] = (qok && jb + r < je) ? Lp[(jb + r) + (int64_t)(k0 + q) * f.nf] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      As[u * NT + tid] = va[u];
-      Bs[u * NT + tid] = vb[u];
-    }
-  }
-  __syncthreads();
+        for (int r = 0; r < 4; r++) {
+          const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
+          const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || ia + i >= ja + j);
+          cv[a][b][r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
+        }
+  };
   typename MF<T>::acc acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
     for (int b = 0; b < 2; b++) acc[a][b] = MF<T>::zero();
+  // operand staging: thread = (row r = tid % 64, column residue c = tid / 64); rows
+  // beyond the tile are clamped (they only feed outputs that are not written),
+  // columns beyond the depth are zeroed
+  constexpr int UL = kTile * kNB / NT;   // loads of each operand per thread and chunk
+  const int r = tid & 63, c4 = tid >> 6;
+  const T* pA = Lp + min(ia + r, ie - 1);
+  const T* pB = Wp + min(ja + r, je - 1);
+  T va[UL], vb[UL];
+  auto load = [&](int q0) {
+#pragma unroll
+    for (int u = 0; u < UL; u++) {
+      const int q = q0 + c4 + 4 * u;
+      const int64_t off = (int64_t)min(q, K - 1) * f.nf;
+      va[u] = pA[off];
+      vb[u] = pB[off];
+      if (q >= K) { va[u] = 0.0; vb[u] = 0.0; }
+    }
+  };
+  const bool direct = nseg == 1;
+  if (K > Kb) load(Kb); else if (direct) load_c();
   const int m = lane & 15, kk = lane >> 4;
-  for (int q0 = 0; q0 < kNB; q0 += 4) {
-    T wv[2], lv[2];
+  for (int q0 = Kb; q0 < K; q0 += kNB) {
+    __syncthreads();   // the previous chunk has been consumed
 #pragma unroll
-    for (int a = 0; a < 2; a++) wv[a] = As[(wr + a * 16 + m) + (q0 + kk) * kTile];
+    for (int u = 0; u < UL; u++) {
+      As[r + (c4 + 4 * u) * kTile] = va[u];
+      Bs[r + (c4 + 4 * u) * kTile] = vb[u];
+    }
+    __syncthreads();
+    if (q0 + kNB < K) load(q0 + kNB); else if (direct) load_c();
+    for (int qq = 0; qq < kNB; qq += 4) {
+      T av[2], bv[2];
 #pragma unroll
-    for (int b = 0; b < 2; b++) lv[b] = Bs[(wc + b * 16 + m) + (q0 + kk) * kTile];
-    // D(m = j, n = i) = sum_q L(j, q) W(i, q)
+      for (int a = 0; a < 2; a++) av[a] = As[(wr + a * 16 + m) + (qq + kk) * kTile];
+#pragma unroll
+      for (int b = 0; b < 2; b++) bv[b] = Bs[(wc + b * 16 + m) + (qq + kk) * kTile];
+      // D(m = j, n = i) = sum_q B(j, q) A(i, q)
+#pragma unroll
+      for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = MF<T>::step(bv[b], av[a], acc[a][b]);
+    }
+  }
+  if (!direct) {
+    T* P = part + (int64_t)g * (kTile * kTile);
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
       for (int b = 0; b < 2; b++)
-        acc[a][b] = MF<T>::step(lv[b], wv[a], acc[a][b]);
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          P[(wr + a * 16 + il) + (wc + b * 16 + MF<T>::mrow(r, lane)) * kTile] = acc[a][b][r];
+    return;
   }
-  // write back: C(i, j) -= acc for i >= j inside the chunk bounds
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -944,9 +968,47 @@ __global__ __launch_bounds__(NT) void k_schur(FrontMeta M, const int32_t* fronts
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
-        const bool ok = (ib + i < ie) && (jb + j < je) && (!diag || i >= j);
+        const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || ia + i >= ja + j);
         if (ok) Cb[i + (int64_t)j * ldc] = cv[a][b][r] - acc[a][b][r];
       }
+}
+
+// C -= sum of the nseg depth segments of each output tile (in segment order) for
+// the split left-looking column-block updates; one entry per thread, workgroup
+// g covers entries [256 (g % 16), 256 (g % 16 + 1)) of output tile g / 16.
+template <int NT, typename T>
+__global__ __launch_bounds__(NT) void k_gemm_reduce(FrontMeta M, const Int2* tasks, int t,
+                                                    int nseg, Batch bt, T* L, const T* part) {
+  static_assert(NT * 16 == kTile * kTile, "one entry per thread");
+  {
+    const int64_t bidx = blockIdx.y;
+    L += bidx * bt.sL;
+    part += bidx * bt.sP;
+  }
+  const int o = blockIdx.x >> 4;
+  const int x = (blockIdx.x & 15) * NT + threadIdx.x;
+  const Int2 tk = tasks[o];
+  const int s = tk.a;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB, kb = min(kNB, ns - k0);
+  const int ia = tk.b, ie = min(ia + kTile, nf);
+  const bool tri = (ia == k0);
+  const int i = x % kTile, j = x / kTile;
+  if (ia + i >= ie || j >= kb || (tri && i < j)) return;
+  const T* P = part + (int64_t)o * nseg * (kTile * kTile) + x;
+  T sum = 0.0;
+  for (int q0 = 0; q0 < nseg; q0 += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = P[(int64_t)min(q0 + u, nseg - 1) * (kTile * kTile)];
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+      if (q0 + u < nseg) sum += v[u];
+  }
+  T* Cb = L + M.lptr[s] + ia + (int64_t)k0 * nf;
+  Cb[i + (int64_t)j * nf] -= sum;
 }
 
 __global__ void k_set_scalar(double* p, double v) {
@@ -1027,13 +1089,21 @@ void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int
 }
 
 template <typename T>
-void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile_prefix,
-                  int32_t nfronts, int32_t ntiles, int32_t t, int mode, const Batch& bt, int nb,
-                  T* L, T* U, const T* W, hipStream_t s) {
-  const int32_t grid = mode == 1 ? nfronts : ntiles;
-  if (grid <= 0) return;
-  hipLaunchKernelGGL((k_schur<256, T>), dim3(grid, nb), dim3(256), 0, s, M, fronts, tile_prefix,
-                     nfronts, t, mode, bt, L, U, W);
+void launch_gemm_lt(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int mode,
+                    int nseg, const Batch& bt, int nb, T* L, T* U, const T* W, T* part,
+                    hipStream_t s) {
+  if (count <= 0) return;
+  if (mode == 2) nseg = 1;
+  hipLaunchKernelGGL((k_gemm_lt<256, T>), dim3(count * nseg, nb), dim3(256), 0, s, M, tasks, t, mode,
+                     nseg, bt, L, U, W, part);
+}
+
+template <typename T>
+void launch_gemm_reduce(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int nseg,
+                        const Batch& bt, int nb, T* L, const T* part, hipStream_t s) {
+  if (count <= 0 || nseg <= 1) return;
+  hipLaunchKernelGGL((k_gemm_reduce<256, T>), dim3(count * 16, nb), dim3(256), 0, s, M, tasks, t,
+                     nseg, bt, L, part);
 }
 
 #define KTH_INSTANTIATE_FACTOR(T)                                                                   \
@@ -1048,8 +1118,10 @@ void launch_schur(const FrontMeta& M, const int32_t* fronts, const int32_t* tile
   template void launch_panel_trsm<T>(const FrontMeta&, const Int2*, int32_t, int32_t, const Batch&, \
                                      int, T*, T*, const double*, const double*, const int32_t*,     \
                                      const T*, FactStats*, hipStream_t);                            \
-  template void launch_schur<T>(const FrontMeta&, const int32_t*, const int32_t*, int32_t, int32_t, \
-                                int32_t, int, const Batch&, int, T*, T*, const T*, hipStream_t);
+  template void launch_gemm_lt<T>(const FrontMeta&, const Int2*, int32_t, int32_t, int, int,         \
+                                  const Batch&, int, T*, T*, const T*, T*, hipStream_t);            \
+  template void launch_gemm_reduce<T>(const FrontMeta&, const Int2*, int32_t, int32_t, int,         \
+                                      const Batch&, int, T*, const T*, hipStream_t);
 KTH_INSTANTIATE_FACTOR(double)
 KTH_INSTANTIATE_FACTOR(float)
 #undef KTH_INSTANTIATE_FACTOR
