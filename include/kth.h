@@ -9,10 +9,9 @@
  *   - Every call returns kth_status; nothing throws across the ABI.  On failure a
  *     message is kept per context (kth_last_error).
  *   - Matrices: CSR with BOTH triangles stored, 0-based, int64 row pointers,
- *     int32 column indices strictly increasing within each row, float64 values,
- *     diagonal entries present.  A and B are given on ONE shared pattern (store
- *     explicit zeros where one of them has no entry); the pattern must be
- *     structurally symmetric.
+ *     int32 column indices strictly increasing within each row, float64 values.
+ *     A and B may have different patterns: the library analyses their union,
+ *     which must hold every diagonal entry and be structurally symmetric.
  *   - Host pointers unless a flag says otherwise.  The library copies what it
  *     needs; the caller may free its arrays on return.  Output buffers are owned
  *     by the caller.  Handles are owned by the library and freed by *_destroy.
@@ -53,8 +52,8 @@ typedef void* (*kth_alloc_fn)(size_t bytes, void* user);
 typedef void (*kth_free_fn)(void* ptr, void* user);
 
 /* pencil flags */
-#define KTH_DEVICE_PTRS    1u  /* value arrays of kth_pencil_set_values are device pointers */
-#define KTH_CHECK_SYMMETRY 2u  /* verify structural symmetry of the pattern (O(nnz log)) */
+#define KTH_DEVICE_PTRS    1u  /* arrays of kth_pencil_create / kth_pencil_set_values are device pointers */
+#define KTH_CHECK_SYMMETRY 2u  /* verify structural symmetry of the union pattern (O(nnz log)) */
 /* solve flags (with KTH_DEVICE_PTRS) */
 #define KTH_SOLVE_UNREFINED 4u /* FP32 factor: one solve pass in the factor's precision, no refinement */
 
@@ -81,13 +80,17 @@ const char* kth_last_error(kth_ctx ctx);   /* message of the last failing call o
 kth_status kth_analyze(int64_t n, const int64_t* rowptr, const int32_t* col, uint32_t flags,
                        double* stats, int64_t* perm_out);
 
-/* Create a pencil.  Ordering and symbolic analysis run here on the host
- * (Section 3.3: they depend on the pattern only and are reused for B and every
- * shift); values and maps are uploaded.  Pattern/values as described above. */
-kth_status kth_pencil_create(kth_ctx ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
-                             const double* a_val, const double* b_val, uint32_t flags,
-                             kth_pencil* out);
-/* Replace the values (same pattern; the analysis is kept).  flags: KTH_DEVICE_PTRS. */
+/* Create a pencil from A (a_rowptr, a_col, a_val) and B (b_rowptr, b_col, b_val).
+ * Ordering and symbolic analysis run here on the host, on the union of the two
+ * patterns (Section 3.3: they depend on the pattern only and are reused for B and
+ * every shift); values and maps are uploaded.  With KTH_DEVICE_PTRS all six arrays
+ * are device pointers (they are copied to the host for the analysis).  The
+ * library keeps its own copies. */
+kth_status kth_pencil_create(kth_ctx ctx, int64_t n, const int64_t* a_rowptr, const int32_t* a_col,
+                             const double* a_val, const int64_t* b_rowptr, const int32_t* b_col,
+                             const double* b_val, uint32_t flags, kth_pencil* out);
+/* Replace the values (same patterns; the analysis is kept): a_val on A's pattern,
+ * b_val on B's.  flags: KTH_DEVICE_PTRS. */
 kth_status kth_pencil_set_values(kth_pencil p, const double* a_val, const double* b_val,
                                  uint32_t flags);
 kth_status kth_pencil_destroy(kth_pencil p);
@@ -173,8 +176,9 @@ kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int
                          const kth_opts* opts, double* lambda, double* const* x, kth_info* info,
                          kth_status* per_pencil);
 /* Hellmann-Feynman backward of a simple eigenvalue: for each STORED entry q
- * (row r, column c): grad_a[q] = g * x_r * x_c and grad_b[q] = -g * lambda * x_r * x_c,
- * x B-normalised.  x, grad_a, grad_b: host arrays (n, nnz, nnz). */
+ * (row r, column c): grad_a[q] = g * x_r * x_c over A's pattern and
+ * grad_b[q] = -g * lambda * x_r * x_c over B's, x B-normalised.  x, grad_a,
+ * grad_b: host arrays (n, nnz of A, nnz of B). */
 kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double g,
                             double* grad_a, double* grad_b);
 

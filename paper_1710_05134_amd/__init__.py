@@ -84,7 +84,8 @@ def lib() -> C.CDLL:
         "kth_status_string": ([C.c_int], C.c_char_p),
         "kth_last_error": ([vp], C.c_char_p),
         "kth_analyze": ([C.c_int64, p64, pi32, C.c_uint32, pd, p64], C.c_int),
-        "kth_pencil_create": ([vp, C.c_int64, p64, pi32, pd, pd, C.c_uint32, C.POINTER(vp)], C.c_int),
+        "kth_pencil_create": ([vp, C.c_int64, p64, pi32, pd, p64, pi32, pd, C.c_uint32, C.POINTER(vp)],
+                              C.c_int),
         "kth_pencil_set_values": ([vp, vp, vp, C.c_uint32], C.c_int),
         "kth_pencil_destroy": ([vp], C.c_int),
         "kth_inertia": ([vp, C.c_double, p64, p64], C.c_int),
@@ -156,19 +157,27 @@ class Context:
 
 
 class Pencil:
-    """kth_pencil over a CSR pattern with both triangles stored."""
+    """kth_pencil: A on (rowptr, col), B on (b_rowptr, b_col) -- by default the same
+    pattern; both triangles stored."""
 
-    def __init__(self, ctx: Context, rowptr, col, a_val, b_val, check_symmetry=False):
+    def __init__(self, ctx: Context, rowptr, col, a_val, b_val, check_symmetry=False,
+                 b_rowptr=None, b_col=None):
         self.ctx = ctx
         self.rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.b_rowptr = self.rowptr if b_rowptr is None else np.ascontiguousarray(b_rowptr, dtype=np.int64)
+        self.b_col = self.col if b_col is None else np.ascontiguousarray(b_col, dtype=np.int32)
         self.n = self.rowptr.size - 1
-        self.nnz = int(self.rowptr[-1])
+        self.nnz = int(self.rowptr[-1])          # entries of A's pattern
+        self.nnz_b = int(self.b_rowptr[-1])      # entries of B's pattern
         a = np.ascontiguousarray(a_val, dtype=np.float64)
         b = np.ascontiguousarray(b_val, dtype=np.float64)
+        if a.size != self.nnz or b.size != self.nnz_b:
+            raise ValueError("value arrays do not match their patterns")
         h = C.c_void_p()
         _check(lib().kth_pencil_create(ctx.h, self.n, _p(self.rowptr, C.c_int64),
                                        _p(self.col, C.c_int32), _p(a, C.c_double),
+                                       _p(self.b_rowptr, C.c_int64), _p(self.b_col, C.c_int32),
                                        _p(b, C.c_double),
                                        KTH_CHECK_SYMMETRY if check_symmetry else 0, C.byref(h)),
                ctx.h)
@@ -233,7 +242,7 @@ class Pencil:
     def backward(self, lam: float, x, g: float = 1.0):
         x = np.ascontiguousarray(x, dtype=np.float64)
         ga = np.zeros(self.nnz)
-        gb = np.zeros(self.nnz)
+        gb = np.zeros(self.nnz_b)
         _check(lib().kth_eig_backward(self.h, float(lam), _p(x, C.c_double), float(g),
                                       _p(ga, C.c_double), _p(gb, C.c_double)), self.ctx.h)
         return ga, gb
@@ -342,3 +351,27 @@ def kth_debug_mfma_probe(A, B):
     D = np.zeros(256)
     _check(lib().kth_debug_mfma_probe(_p(A, C.c_double), _p(B, C.c_double), _p(D, C.c_double)))
     return D
+
+
+def eig_function():
+    """torch.autograd.Function over (a_val, b_val) -> lambda_k: forward through kth_eig on
+    the pencil's pattern(s), backward through kth_eig_backward (Hellmann-Feynman).
+    Tensors are float64 on the host (PyTorch only carries them).  Usage:
+        F = eig_function(); lam = F.apply(a, b, pencil, k, opts_or_None)"""
+    import torch
+
+    class KthEig(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, a_val, b_val, pencil, k, opts):
+            pencil.set_values(a_val.detach().to("cpu", torch.float64).numpy(),
+                              b_val.detach().to("cpu", torch.float64).numpy())
+            lam, x, _ = pencil.eig(int(k), opts=opts)
+            ctx.pencil, ctx.lam, ctx.x = pencil, lam, x
+            return torch.tensor(lam, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            ga, gb = ctx.pencil.backward(ctx.lam, ctx.x, float(g))
+            return torch.from_numpy(ga), torch.from_numpy(gb), None, None, None
+
+    return KthEig

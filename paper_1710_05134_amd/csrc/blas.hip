@@ -215,6 +215,13 @@ __global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double
     y[i] = fma(a, x[i], y[i]);
 }
 
+// out[map[i]] = in[i]: values of one pattern placed into the union pattern
+__global__ void k_scatter_values(int64_t m, const int64_t* __restrict__ map,
+                                 const double* __restrict__ in, double* out) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < m; i += (int64_t)gridDim.x * NT)
+    out[map[i]] = in[i];
+}
+
 // Hellmann-Feynman: per stored entry q of row r: ga = g x_r x_c, gb = -g lam x_r x_c
 __global__ __launch_bounds__(NT) void k_hf(int64_t n, const int64_t* __restrict__ rowptr,
                                            const int32_t* __restrict__ col, const double* __restrict__ x,
@@ -435,6 +442,11 @@ void absmax(int64_t n, const double* x, double* partial, double* out, hipStream_
 
 void axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n, NT * 4)), dim3(NT), 0, s, n, a, x, y);
+}
+
+void scatter_values(int64_t m, const int64_t* map, const double* in, double* out, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_scatter_values, dim3(blocks_for(m, NT * 4)), dim3(NT), 0, s, m, map, in, out);
 }
 
 void hf_gradient(int64_t n, const int64_t* rowptr, const int32_t* col, const double* x, double g,

@@ -176,18 +176,35 @@ kth_status kth_analyze(int64_t n, const int64_t* rowptr, const int32_t* col, uin
   });
 }
 
-kth_status kth_pencil_create(kth_ctx ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
-                             const double* a_val, const double* b_val, uint32_t flags,
-                             kth_pencil* out) {
+kth_status kth_pencil_create(kth_ctx ctx, int64_t n, const int64_t* a_rowptr, const int32_t* a_col,
+                             const double* a_val, const int64_t* b_rowptr, const int32_t* b_col,
+                             const double* b_val, uint32_t flags, kth_pencil* out) {
   if (!ctx || !out) return KTH_EINVAL;
   *out = nullptr;
   std::unique_ptr<kth_pencil_s> p(new kth_pencil_s());
   p->ctx = ctx;
   kth_status st = guarded(&ctx->c, [&] {
-    if (!rowptr || !col || !a_val || !b_val) throw Error(KTH_EINVAL, "null argument");
-    if (flags & KTH_DEVICE_PTRS) throw Error(KTH_EINVAL, "kth_pencil_create takes host arrays");
+    if (!a_rowptr || !a_col || !a_val || !b_rowptr || !b_col || !b_val)
+      throw Error(KTH_EINVAL, "null argument");
+    if (n <= 0) throw Error(KTH_EINVAL, "n must be positive");
     set_device(ctx->c);
-    pencil_init(p->p, &ctx->c, n, rowptr, col, a_val, b_val, flags);
+    if (flags & KTH_DEVICE_PTRS) {
+      // device inputs: the analysis runs on the host, so bring them over first
+      std::vector<int64_t> arp(n + 1), brp(n + 1);
+      KTH_HIP(hipMemcpy(arp.data(), a_rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+      KTH_HIP(hipMemcpy(brp.data(), b_rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+      if (arp[n] < 0 || brp[n] < 0) throw Error(KTH_EINVAL, "rowptr[n] is negative");
+      std::vector<int32_t> ac(arp[n]), bc(brp[n]);
+      std::vector<double> av(arp[n]), bv(brp[n]);
+      KTH_HIP(hipMemcpy(ac.data(), a_col, sizeof(int32_t) * arp[n], hipMemcpyDeviceToHost));
+      KTH_HIP(hipMemcpy(bc.data(), b_col, sizeof(int32_t) * brp[n], hipMemcpyDeviceToHost));
+      KTH_HIP(hipMemcpy(av.data(), a_val, sizeof(double) * arp[n], hipMemcpyDeviceToHost));
+      KTH_HIP(hipMemcpy(bv.data(), b_val, sizeof(double) * brp[n], hipMemcpyDeviceToHost));
+      pencil_init(p->p, &ctx->c, n, arp.data(), ac.data(), av.data(), brp.data(), bc.data(), bv.data(),
+                  flags);
+    } else {
+      pencil_init(p->p, &ctx->c, n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, flags);
+    }
   });
   if (st == KTH_OK) {
     ctx->refs++;

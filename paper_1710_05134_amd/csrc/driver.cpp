@@ -730,8 +730,17 @@ void hf_backward(Pencil& P, double lambda, const double* x, double g, double* ga
   gad.alloc(c, P.nnz);
   gbd.alloc(c, P.nnz);
   hf_gradient(P.n, P.rowptr.get(), P.col.get(), xd.get(), g, lambda, gad.get(), gbd.get(), c->stream);
-  d2h(c, ga, gad.get(), P.nnz);
-  d2h(c, gb, gbd.get(), P.nnz);
+  if (P.h_amap.empty()) {
+    d2h(c, ga, gad.get(), P.nnz);
+    d2h(c, gb, gbd.get(), P.nnz);
+    return;
+  }
+  // union entries back to A's and B's own patterns
+  std::vector<double> ua(P.nnz), ub(P.nnz);
+  d2h(c, ua.data(), gad.get(), P.nnz);
+  d2h(c, ub.data(), gbd.get(), P.nnz);
+  for (int64_t q = 0; q < P.nnz_a; q++) ga[q] = ua[P.h_amap[q]];
+  for (int64_t q = 0; q < P.nnz_b; q++) gb[q] = ub[P.h_bmap[q]];
 }
 
 }  // namespace kth

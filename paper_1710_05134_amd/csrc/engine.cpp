@@ -2,6 +2,8 @@
 // level-by-level launch sequence of the numeric factorization.
 #include "engine.hpp"
 
+#include "blas.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -202,19 +204,71 @@ static void build_schedule(Pencil& P) {
   P.splan.pbase = P.d_pbase.get();
 }
 
-void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
-                 const double* a, const double* b, uint32_t flags) {
+// Rows of one CSR pattern: in range, strictly increasing columns.
+static void check_rows(int64_t n, const int64_t* rp, const int32_t* col, const char* name) {
+  if (!rp || !col) throw Error(KTH_EINVAL, std::string("null pattern of ") + name);
+  if (rp[0] != 0) throw Error(KTH_EINVAL, std::string(name) + ": rowptr[0] must be 0");
+  for (int64_t i = 0; i < n; i++) {
+    if (rp[i + 1] < rp[i]) throw Error(KTH_EINVAL, std::string(name) + ": rowptr is not non-decreasing");
+    for (int64_t q = rp[i]; q < rp[i + 1]; q++) {
+      if (col[q] < 0 || col[q] >= n)
+        throw Error(KTH_EINVAL, std::string(name) + ": column index out of range in row " + std::to_string(i));
+      if (q > rp[i] && col[q - 1] >= col[q])
+        throw Error(KTH_EINVAL, std::string(name) + ": columns not strictly increasing in row " + std::to_string(i));
+    }
+  }
+}
+
+void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* arp, const int32_t* acol,
+                 const double* a, const int64_t* brp, const int32_t* bcol, const double* b,
+                 uint32_t flags) {
   P.ctx = ctx;
   P.n = n;
+  if (n <= 0) throw Error(KTH_EINVAL, "n must be positive");
+  check_rows(n, arp, acol, "A");
+  check_rows(n, brp, bcol, "B");
+  P.nnz_a = arp[n];
+  P.nnz_b = brp[n];
+  const bool same = (arp == brp && acol == bcol) ||
+                    (P.nnz_a == P.nnz_b && std::equal(arp, arp + n + 1, brp) &&
+                     std::equal(acol, acol + P.nnz_a, bcol));
+  P.h_amap.clear();
+  P.h_bmap.clear();
+  if (same) {
+    P.h_rowptr.assign(arp, arp + n + 1);
+    P.h_col.assign(acol, acol + P.nnz_a);
+  } else {
+    // row-wise merge of the two sorted column lists; maps from each pattern into it
+    P.h_rowptr.assign(n + 1, 0);
+    P.h_col.clear();
+    P.h_col.reserve(std::max(P.nnz_a, P.nnz_b));
+    P.h_amap.resize(P.nnz_a);
+    P.h_bmap.resize(P.nnz_b);
+    for (int64_t i = 0; i < n; i++) {
+      int64_t qa = arp[i], qb = brp[i];
+      while (qa < arp[i + 1] || qb < brp[i + 1]) {
+        const int32_t ca = qa < arp[i + 1] ? acol[qa] : INT32_MAX;
+        const int32_t cb = qb < brp[i + 1] ? bcol[qb] : INT32_MAX;
+        const int32_t c = std::min(ca, cb);
+        const int64_t u = (int64_t)P.h_col.size();
+        P.h_col.push_back(c);
+        if (ca == c) P.h_amap[qa++] = u;
+        if (cb == c) P.h_bmap[qb++] = u;
+      }
+      P.h_rowptr[i + 1] = (int64_t)P.h_col.size();
+    }
+  }
+  P.nnz = P.h_rowptr[n];
   Pattern pat;
   pat.n = n;
-  pat.rowptr = rowptr;
-  pat.col = col;
+  pat.rowptr = P.h_rowptr.data();
+  pat.col = P.h_col.data();
   std::string msg = check_pattern(pat, (flags & KTH_CHECK_SYMMETRY) != 0);
   if (!msg.empty()) throw Error(KTH_EINVAL, msg);
-  P.nnz = rowptr[n];
-  P.h_rowptr.assign(rowptr, rowptr + n + 1);
-  P.h_col.assign(col, col + P.nnz);
+  if (!P.h_amap.empty()) {
+    P.d_amap.upload(ctx, P.h_amap);
+    P.d_bmap.upload(ctx, P.h_bmap);
+  }
   pat.rowptr = P.h_rowptr.data();
   pat.col = P.h_col.data();
   AnalysisOpts o;
@@ -279,21 +333,43 @@ void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const in
 }
 
 void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_ptrs) {
+  Ctx* c = P.ctx;
   const size_t bytes = P.nnz * sizeof(double);
-  hipMemcpyKind kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  KTH_HIP(hipMemcpyAsync(P.aval.get(), a, bytes, kind, P.ctx->stream));
-  KTH_HIP(hipMemcpyAsync(P.bval.get(), b, bytes, kind, P.ctx->stream));
-  if (!device_ptrs) {
+  if (P.h_amap.empty() && !device_ptrs) {
+    KTH_HIP(hipMemcpyAsync(P.aval.get(), a, bytes, hipMemcpyHostToDevice, c->stream));
+    KTH_HIP(hipMemcpyAsync(P.bval.get(), b, bytes, hipMemcpyHostToDevice, c->stream));
     P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), a);
     P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), b);
-  } else {
-    std::vector<double> ha(P.nnz), hb(P.nnz);
-    KTH_HIP(hipMemcpyAsync(ha.data(), a, bytes, hipMemcpyDeviceToHost, P.ctx->stream));
-    KTH_HIP(hipMemcpyAsync(hb.data(), b, bytes, hipMemcpyDeviceToHost, P.ctx->stream));
-    P.ctx->sync();
-    P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), ha.data());
-    P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), hb.data());
+    c->sync();
+    return;
   }
+  if (!device_ptrs) {
+    std::vector<double> ua(P.nnz, 0.0), ub(P.nnz, 0.0);
+    for (int64_t q = 0; q < P.nnz_a; q++) ua[P.h_amap[q]] = a[q];
+    for (int64_t q = 0; q < P.nnz_b; q++) ub[P.h_bmap[q]] = b[q];
+    KTH_HIP(hipMemcpyAsync(P.aval.get(), ua.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    KTH_HIP(hipMemcpyAsync(P.bval.get(), ub.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), ua.data());
+    P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), ub.data());
+    c->sync();   // the host staging arrays go out of scope
+    return;
+  }
+  if (P.h_amap.empty()) {
+    KTH_HIP(hipMemcpyAsync(P.aval.get(), a, bytes, hipMemcpyDeviceToDevice, c->stream));
+    KTH_HIP(hipMemcpyAsync(P.bval.get(), b, bytes, hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    KTH_HIP(hipMemsetAsync(P.aval.get(), 0, bytes, c->stream));
+    KTH_HIP(hipMemsetAsync(P.bval.get(), 0, bytes, c->stream));
+    scatter_values(P.nnz_a, P.d_amap.get(), a, P.aval.get(), c->stream);
+    scatter_values(P.nnz_b, P.d_bmap.get(), b, P.bval.get(), c->stream);
+  }
+  // norms on the union arrays as they now sit on the device
+  std::vector<double> ha(P.nnz), hb(P.nnz);
+  KTH_HIP(hipMemcpyAsync(ha.data(), P.aval.get(), bytes, hipMemcpyDeviceToHost, c->stream));
+  KTH_HIP(hipMemcpyAsync(hb.data(), P.bval.get(), bytes, hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), ha.data());
+  P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), hb.data());
 }
 
 static void ensure_workspace(Pencil& P, int nb) {

@@ -106,8 +106,12 @@ struct Pencil {
   Ctx* ctx = nullptr;
   int64_t n = 0, nnz = 0;
   Symbolic S;
-  std::vector<int64_t> h_rowptr;
+  std::vector<int64_t> h_rowptr;   // union of the patterns of A and B
   std::vector<int32_t> h_col;
+  // A's and B's own patterns inside the union (empty maps: both patterns equal it)
+  int64_t nnz_a = 0, nnz_b = 0;
+  std::vector<int64_t> h_amap, h_bmap;
+  DBuf<int64_t> d_amap, d_bmap;
   double normA_inf = 0, normB_inf = 0;
   // device CSR and values
   DBuf<int64_t> rowptr;
@@ -165,8 +169,11 @@ struct FactorProfile {
   ~FactorProfile();
 };
 
-void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* col,
-                 const double* a, const double* b, uint32_t flags);
+// Host arrays: A on (arp, acol), B on (brp, bcol); the union pattern is analysed.
+void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* arp, const int32_t* acol,
+                 const double* a, const int64_t* brp, const int32_t* bcol, const double* b,
+                 uint32_t flags);
+// a: nnz_a values on A's pattern, b: nnz_b on B's (host, or device with device_ptrs).
 void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_ptrs);
 void factor_alloc(Pencil& P, NumFactor& F, int nb = 1, kth_precision prec = KTH_FP64);
 // Largest batch of factorizations that fits in free device memory (<= cap).

@@ -852,8 +852,9 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
     L += bidx * bt.sL; U += bidx * bt.sU; W += bidx * bt.sW;
     part += bidx * bt.sP;
   }
-  __shared__ T As[kTile * kNB];  // A rows (i) x q, ld kTile
-  __shared__ T Bs[kTile * kNB];  // B rows (j) x q, ld kTile
+  constexpr int KC = 16;         // depth chunk staged through LDS
+  __shared__ T As[kTile * KC];   // A rows (i) x q, ld kTile
+  __shared__ T Bs[kTile * KC];   // B rows (j) x q, ld kTile
   const int g = blockIdx.x;
   const int seg = g % nseg;
   const Int2 tk = tasks[g / nseg];
@@ -889,19 +890,6 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
   // Output layout with A = rows i and B = rows j: lane l holds i = l % 16 of its
   // block and j = mrow(r, l) for register r -> 16 consecutive rows per column.
   const int il = lane & 15;
-  T cv[2][2][4];   // C entries of this thread, loaded during the last depth chunk
-  auto load_c = [&]() {
-#pragma unroll
-    for (int a = 0; a < 2; a++)
-#pragma unroll
-      for (int b = 0; b < 2; b++)
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-          const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
-          const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || ia + i >= ja + j);
-          cv[a][b][r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
-        }
-  };
   typename MF<T>::acc acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; a++)
@@ -910,7 +898,7 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
   // operand staging: thread = (row r = tid % 64, column residue c = tid / 64); rows
   // beyond the tile are clamped (they only feed outputs that are not written),
   // columns beyond the depth are zeroed
-  constexpr int UL = kTile * kNB / NT;   // loads of each operand per thread and chunk
+  constexpr int UL = kTile * KC / NT;    // loads of each operand per thread and chunk
   const int r = tid & 63, c4 = tid >> 6;
   const T* pA = Lp + min(ia + r, ie - 1);
   const T* pB = Wp + min(ja + r, je - 1);
@@ -926,9 +914,9 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
     }
   };
   const bool direct = nseg == 1;
-  if (K > Kb) load(Kb); else if (direct) load_c();
+  if (K > Kb) load(Kb);
   const int m = lane & 15, kk = lane >> 4;
-  for (int q0 = Kb; q0 < K; q0 += kNB) {
+  for (int q0 = Kb; q0 < K; q0 += KC) {
     __syncthreads();   // the previous chunk has been consumed
 #pragma unroll
     for (int u = 0; u < UL; u++) {
@@ -936,8 +924,9 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
       Bs[r + (c4 + 4 * u) * kTile] = vb[u];
     }
     __syncthreads();
-    if (q0 + kNB < K) load(q0 + kNB); else if (direct) load_c();
-    for (int qq = 0; qq < kNB; qq += 4) {
+    if (q0 + KC < K) load(q0 + KC);
+#pragma unroll
+    for (int qq = 0; qq < KC; qq += 4) {
       T av[2], bv[2];
 #pragma unroll
       for (int a = 0; a < 2; a++) av[a] = As[(wr + a * 16 + m) + (qq + kk) * kTile];
@@ -961,16 +950,25 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
           P[(wr + a * 16 + il) + (wc + b * 16 + MF<T>::mrow(r, lane)) * kTile] = acc[a][b][r];
     return;
   }
+  // C -= product, read after the depth loop (keeps the loop's registers free)
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++)
+    for (int b = 0; b < 2; b++) {
+      T cv[4];
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
         const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || ia + i >= ja + j);
-        if (ok) Cb[i + (int64_t)j * ldc] = cv[a][b][r] - acc[a][b][r];
+        cv[r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
       }
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
+        const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || ia + i >= ja + j);
+        if (ok) Cb[i + (int64_t)j * ldc] = cv[r] - acc[a][b][r];
+      }
+    }
 }
 
 // C -= sum of the nseg depth segments of each output tile (in segment order) for

@@ -189,3 +189,76 @@ def test_option_validation(K, ctx):
         with pytest.raises(K.KthError) as e:
             P.eig(p.n // 2, **bad)
         assert e.value.status == K.KTH_EINVAL, bad
+
+
+def _sub_pattern(p, keep):
+    """CSR of the entries of p's pattern selected by the boolean mask keep."""
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    rp = np.zeros(p.n + 1, dtype=np.int64)
+    np.add.at(rp, rows[keep] + 1, 1)
+    return np.cumsum(rp), p.col[keep].astype(np.int32)
+
+
+def test_separate_patterns(K, ctx):
+    # B on its nonzero entries only, A on the full pattern (and the converse): the
+    # union is the full pattern, so every result equals the shared-pattern pencil's
+    p = pg.tb_supercell((2, 2, 3), seed=8)
+    note("separate A / B patterns")
+    full = K.Pencil.from_pencilgen(ctx, p)
+    kb = p.b_val != 0.0
+    ka = p.a_val != 0.0
+    assert kb.sum() < p.nnz and ka.sum() < p.nnz
+    brp, bcol = _sub_pattern(p, kb)
+    arp, acol = _sub_pattern(p, ka)
+    PB = K.Pencil(ctx, p.rowptr, p.col, p.a_val, p.b_val[kb], b_rowptr=brp, b_col=bcol)
+    PA = K.Pencil(ctx, arp, acol, p.a_val[ka], p.b_val, b_rowptr=p.rowptr, b_col=p.col)
+    lam, _ = od.eig(p)
+    for s in np.linspace(lam[0] - 0.3, lam[-1] + 0.3, 9):
+        assert full.nu(s) == PB.nu(s) == PA.nu(s) == od.nu(lam, s)
+    k = p.n // 2
+    sv = pg.start_vectors(p.n)
+    l0, x0, _ = full.eig(k, start_vectors=sv)
+    l1, x1, _ = PB.eig(k, start_vectors=sv)
+    l2, x2, _ = PA.eig(k, start_vectors=sv)
+    assert l0 == l1 == l2 and np.array_equal(x0, x1) and np.array_equal(x0, x2)
+    ga0, gb0 = full.backward(l0, x0)
+    ga1, gb1 = PB.backward(l0, x0)
+    ga2, gb2 = PA.backward(l0, x0)
+    assert np.array_equal(ga1, ga0) and np.array_equal(gb1, gb0[kb])
+    assert np.array_equal(ga2, ga0[ka]) and np.array_equal(gb2, gb0)
+    # new values on the separate patterns: the spectrum doubles
+    PB.set_values(2.0 * p.a_val, p.b_val[kb])
+    for s in np.linspace(2 * lam[0] - 0.3, 2 * lam[-1] + 0.3, 7):
+        assert PB.nu(s) == od.nu(2.0 * lam, s)
+
+
+def test_pencil_create_device_pointers(K, ctx):
+    import ctypes
+    p = pg.tb_supercell((2, 2, 2), seed=9)
+    note("device-pointer pencil create")
+    host = K.Pencil.from_pencilgen(ctx, p)
+    hip = _hip()
+    arrs = [np.ascontiguousarray(p.rowptr, dtype=np.int64), np.ascontiguousarray(p.col, dtype=np.int32),
+            np.ascontiguousarray(p.a_val), np.ascontiguousarray(p.b_val)]
+    dev = [ctypes.c_void_p() for _ in arrs]
+    try:
+        for a, d in zip(arrs, dev):
+            assert hip.hipMalloc(ctypes.byref(d), a.nbytes) == 0
+            assert hip.hipMemcpy(d, a.ctypes.data, a.nbytes, 1) == 0
+        h = ctypes.c_void_p()
+        P64, P32, PD = (ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                        ctypes.POINTER(ctypes.c_double))
+        K._check(K.lib().kth_pencil_create(
+            ctx.h, p.n, ctypes.cast(dev[0].value, P64), ctypes.cast(dev[1].value, P32),
+            ctypes.cast(dev[2].value, PD), ctypes.cast(dev[0].value, P64), ctypes.cast(dev[1].value, P32),
+            ctypes.cast(dev[3].value, PD), K.KTH_DEVICE_PTRS, ctypes.byref(h)), ctx.h)
+        try:
+            for s in (-4.0, -2.5, 0.5):
+                nu, nz = ctypes.c_int64(), ctypes.c_int64()
+                K._check(K.lib().kth_inertia(h, s, ctypes.byref(nu), ctypes.byref(nz)), ctx.h)
+                assert nu.value == host.nu(s)
+        finally:
+            K.lib().kth_pencil_destroy(h)
+    finally:
+        for d in dev:
+            hip.hipFree(d)
