@@ -141,6 +141,8 @@ typedef struct {
   const double* warm_interval; /* optional [2]: sigma_l, sigma_u (skip stages 1-2)             */
   const int64_t* warm_counts;  /* optional [2]: nu_l, nu_u matching warm_interval              */
   double ir_tol;          /* FP32 shift-and-invert solves: target backward error (0: 4 eps64) */
+  int32_t batch_workers;  /* kth_eig_batch: pencils solved concurrently, each on its own
+                             streams (0: 8; 1: one after another on the context stream) */
 } kth_opts;
 
 typedef struct {
@@ -171,7 +173,11 @@ void kth_opts_default(kth_opts* o);
  * (x^T B x = 1) with its largest-|.| entry positive.  info (may be NULL). */
 kth_status kth_eig(kth_pencil p, int64_t k, const kth_opts* opts, double* lambda, double* x,
                    kth_info* info);
-/* Many pencils in one call (each with its own k). per_pencil: np statuses. */
+/* Many pencils in one call (each with its own k), all from ctx.  Worker threads
+ * (opts->batch_workers) take the pencils in turn, each on streams of its own that
+ * first wait for the work queued on the context stream; the call returns when all
+ * are done.  per_pencil: np statuses (the call itself returns KTH_OK unless its
+ * arguments are invalid); kth_last_error(ctx) holds one failing pencil's message. */
 kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int64_t* k,
                          const kth_opts* opts, double* lambda, double* const* x, kth_info* info,
                          kth_status* per_pencil);

@@ -37,7 +37,8 @@ class kth_opts(C.Structure):
     _fields_ = [("m_max", C.c_int64), ("tau_res", C.c_double), ("tau_diff", C.c_double),
                 ("tau_len", C.c_double), ("max_lanczos", C.c_int32), ("multisection", C.c_int32),
                 ("seed", C.c_uint64), ("si_precision", C.c_int), ("start_vectors", C.c_void_p),
-                ("warm_interval", C.c_void_p), ("warm_counts", C.c_void_p), ("ir_tol", C.c_double)]
+                ("warm_interval", C.c_void_p), ("warm_counts", C.c_void_p), ("ir_tol", C.c_double),
+                ("batch_workers", C.c_int32)]
 
 
 class kth_info(C.Structure):

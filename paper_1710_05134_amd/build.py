@@ -40,7 +40,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         for src, msg in failed:
             sys.stderr.write(f"--- {src}\n{msg}\n")
         raise RuntimeError("libkth build failed: " + ", ".join(s for s, _ in failed))
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", LIB + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -64,12 +64,16 @@ void check_opts(const kth_opts& o) {
   if (o.si_precision != KTH_FP64 && o.si_precision != KTH_FP32_IR)
     throw Error(KTH_EINVAL, "unknown si_precision");
   if (!(o.ir_tol >= 0) || !std::isfinite(o.ir_tol)) throw Error(KTH_EINVAL, "ir_tol must be >= 0");
+  if (o.batch_workers < 0 || o.batch_workers > 64) throw Error(KTH_EINVAL, "batch_workers must be in [0, 64]");
 }
 
 void ctx_release(kth_ctx_s* c) {
   if (--c->refs > 0) return;
   (void)hipSetDevice(c->c.device);
+  c->c.destroy_workers();
   c->c.destroy_aux();
+  (void)hipStreamSynchronize(c->c.stream);
+  c->c.trim_cache(0);
   if (c->c.own_stream) (void)hipStreamDestroy(c->c.stream);
   delete c;
 }

@@ -21,7 +21,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <mutex>
 #include <numeric>
+#include <thread>
 
 #include "blas.hpp"
 
@@ -709,18 +712,55 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
 
 void eig_batch(Ctx& c, const std::vector<Pencil*>& ps, const int64_t* k, const kth_opts& o,
                double* lambda, double* const* x, kth_info* info, kth_status* per) {
-  for (size_t i = 0; i < ps.size(); i++) {
+  const int np = (int)ps.size();
+  // pencils are independent: worker threads, each on its own streams, take them in
+  // turn so that the short, latency-bound launches of several pencils overlap
+  const int nw = std::min(np, o.batch_workers > 0 ? (int)o.batch_workers : 8);
+  std::mutex err_mu;
+  auto run_one = [&](int i, Ctx* wc) {
     kth_info tmp;
     kth_info* inf = info ? info + i : &tmp;
     std::memset(inf, 0, sizeof(*inf));
+    Pencil& P = *ps[i];
+    Ctx* keep = P.ctx;
+    if (wc) P.ctx = wc;
     try {
-      if (k[i] < 1 || k[i] > ps[i]->n) throw Error(KTH_EINVAL, "k out of range");
-      per[i] = three_stage(*ps[i], k[i], o, lambda + i, x ? x[i] : nullptr, inf);
-    } catch (const Error& e) {
-      per[i] = e.status;
+      if (k[i] < 1 || k[i] > P.n) throw Error(KTH_EINVAL, "k out of range");
+      per[i] = three_stage(P, k[i], o, lambda + i, x ? x[i] : nullptr, inf);
+    } catch (const std::exception& e) {
+      const Error* ke = dynamic_cast<const Error*>(&e);
+      per[i] = ke ? ke->status : KTH_EDEVICE;
+      std::lock_guard<std::mutex> g(err_mu);
       c.last_error = e.what();
     }
+    if (wc) {
+      (void)hipStreamSynchronize(wc->stream);
+      P.ctx = keep;
+    }
+  };
+  if (nw <= 1) {
+    for (int i = 0; i < np; i++) run_one(i, nullptr);
+    return;
   }
+  c.ensure_workers(nw);
+  for (int w = 0; w < nw; w++) {
+    // the workers' kernels must not start before work the caller queued on its stream
+    c.workers[w]->ensure_aux();
+    KTH_HIP(hipEventRecord(c.workers[w]->ev_diag, c.stream));
+    KTH_HIP(hipStreamWaitEvent(c.workers[w]->stream, c.workers[w]->ev_diag, 0));
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; w++)
+    th.emplace_back([&, w]() {
+      (void)hipSetDevice(c.device);
+      for (;;) {
+        const int i = next.fetch_add(1);
+        if (i >= np) break;
+        run_one(i, c.workers[w].get());
+      }
+    });
+  for (auto& t : th) t.join();
 }
 
 void hf_backward(Pencil& P, double lambda, const double* x, double g, double* ga, double* gb) {

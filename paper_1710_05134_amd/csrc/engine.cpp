@@ -10,15 +10,36 @@
 
 namespace kth {
 
+// Default allocator: blocks released by this context are kept for reuse (on this
+// context's stream, so stream order covers any pending use) instead of hipFree,
+// which would synchronise the whole device and stall other contexts' streams.
+static constexpr size_t kCacheLimit = size_t(16) << 30;
+
 void* Ctx::alloc(size_t bytes) {
   void* p = nullptr;
   if (afn) {
     p = afn(bytes, user);
     if (!p) throw Error(KTH_ENOMEM, "device allocator returned NULL for " + std::to_string(bytes) + " bytes");
   } else {
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess || !p)
-      throw Error(KTH_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    // a cached block of at least this size and at most twice it
+    auto it = cache.lower_bound(bytes);
+    if (it != cache.end() && it->first <= 2 * bytes + 4096) {
+      p = it->second.first;
+      const size_t got = it->first;
+      cache_bytes -= got;
+      cache.erase(it);
+      sizes[p] = got;
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if ((e != hipSuccess || !p) && !cache.empty()) {
+        (void)hipGetLastError();
+        trim_cache(0);
+        e = hipMalloc(&p, bytes);
+      }
+      if (e != hipSuccess || !p)
+        throw Error(KTH_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+      sizes[p] = bytes;
+    }
   }
   cur_bytes += (double)bytes;
   peak_bytes = std::max(peak_bytes, cur_bytes);
@@ -27,9 +48,24 @@ void* Ctx::alloc(size_t bytes) {
 
 void Ctx::release(void* p, size_t bytes) {
   if (!p) return;
-  if (ffn) ffn(p, user);
-  else (void)hipFree(p);
   cur_bytes -= (double)bytes;
+  if (ffn) { ffn(p, user); return; }
+  auto it = sizes.find(p);
+  const size_t got = it != sizes.end() ? it->second : bytes;
+  if (it != sizes.end()) sizes.erase(it);
+  cache.emplace(got, std::make_pair(p, 0));
+  cache_bytes += got;
+  if (cache_bytes > kCacheLimit) trim_cache(kCacheLimit / 2);
+}
+
+void Ctx::trim_cache(size_t keep) {
+  // largest blocks first
+  while (!cache.empty() && cache_bytes > keep) {
+    auto it = std::prev(cache.end());
+    (void)hipFree(it->second.first);
+    cache_bytes -= it->first;
+    cache.erase(it);
+  }
 }
 
 void Ctx::sync() { KTH_HIP(hipStreamSynchronize(stream)); }
@@ -39,6 +75,29 @@ void Ctx::ensure_aux() {
   KTH_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
   KTH_HIP(hipEventCreateWithFlags(&ev_diag, hipEventDisableTiming));
   KTH_HIP(hipEventCreateWithFlags(&ev_tile, hipEventDisableTiming));
+}
+
+void Ctx::ensure_workers(int nw) {
+  while ((int)workers.size() < nw) {
+    std::unique_ptr<Ctx> w(new Ctx());
+    w->device = device;
+    w->afn = afn;
+    w->ffn = ffn;
+    w->user = user;
+    KTH_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+    w->own_stream = true;
+    workers.push_back(std::move(w));
+  }
+}
+
+void Ctx::destroy_workers() {
+  for (auto& w : workers) {
+    (void)hipStreamSynchronize(w->stream);
+    w->destroy_aux();
+    w->trim_cache(0);
+    if (w->own_stream) (void)hipStreamDestroy(w->stream);
+  }
+  workers.clear();
 }
 
 void Ctx::destroy_aux() {

@@ -4,9 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -42,11 +44,22 @@ struct Ctx {
   // events that order it against the context stream
   hipStream_t aux = nullptr;
   hipEvent_t ev_diag = nullptr, ev_tile = nullptr;
+  // contexts of the worker threads of kth_eig_batch (own streams, same device and
+  // allocator); they live as long as this context, so buffers they allocate for a
+  // pencil stay releasable
+  std::vector<std::unique_ptr<Ctx>> workers;
+  // released blocks of the default allocator kept for reuse: size -> (pointer, unused)
+  std::multimap<size_t, std::pair<void*, int>> cache;
+  std::unordered_map<void*, size_t> sizes;   // size of every block handed out
+  size_t cache_bytes = 0;
   void* alloc(size_t bytes);
   void release(void* p, size_t bytes);
+  void trim_cache(size_t keep);   // hipFree cached blocks (largest first) down to keep bytes
   void sync();
   void ensure_aux();
   void destroy_aux();
+  void ensure_workers(int nw);
+  void destroy_workers();
 };
 
 // Device buffer owned through the context's allocator.

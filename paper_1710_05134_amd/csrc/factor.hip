@@ -1049,13 +1049,13 @@ void launch_small_fronts(const FrontMeta& M, const int32_t* fronts, int32_t coun
                          FactStats* st, hipStream_t s) {
   if (count <= 0) return;
   const size_t lds = (size_t)max_nf * max_nf * sizeof(T);
-  static bool attr = false;
-  if (!attr) {
+  static const bool attr = [] {   // once per type, thread-safe
     (void)hipFuncSetAttribute((const void*)k_small_fronts<256, T>,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               kSmallMaxNf * kSmallMaxNf * (int)sizeof(T));
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   hipLaunchKernelGGL((k_small_fronts<256, T>), dim3(count, nb), dim3(256), lds, s, M, fronts, aval,
                      bval, bt, L, U, D, E, tperm, st);
 }
