@@ -79,3 +79,23 @@ def test_eig_batch_uneven_pencils(K, ctx):
         lam_ref, _ = od.kth(p, p.k)
         assert info["k_validated"] == p.k
         assert abs(lam - lam_ref) <= 1e-10 * od.norm_inf(p)
+
+
+def test_eig_batch_workers_match_sequential(K, ctx):
+    # concurrent workers give the same results as one pencil after another, and a
+    # bad k fails only its own pencil
+    ps = pg.uneven_batch(12, seed=3, n_lo=300, n_hi=1500)
+    note(f"eig batch workers vs sequential, n {[p.n for p in ps]}")
+    Ps = [K.Pencil.from_pencilgen(ctx, p) for p in ps]
+    ks = [p.k for p in ps]
+    ks[5] = ps[5].n + 1                      # invalid
+    seq = K.eig_batch(ctx, Ps, ks, batch_workers=1)
+    par = K.eig_batch(ctx, Ps, ks, batch_workers=6)
+    for i, (a, b) in enumerate(zip(seq, par)):
+        if i == 5:
+            assert a[0] == b[0] == K.KTH_EINVAL
+            continue
+        assert a[0] == b[0] == K.KTH_OK
+        assert a[1] == b[1] and np.array_equal(a[2], b[2])
+        assert a[3]["k_validated"] == b[3]["k_validated"] == ks[i]
+        assert a[3]["sigmas"] == b[3]["sigmas"]

@@ -158,3 +158,21 @@ def test_eig_fp32_n131k_golden(K, ctx):
     assert info["k_validated"] == p.k
     assert abs(lam - g["lam"]) <= 1e-10 * nA
     assert info["rel_residual_normA"] <= 1e-9
+
+
+def test_fp32_unrefined_solve(K, ctx):
+    # KTH_SOLVE_UNREFINED applies the FP32 factor once: FP32-level backward error,
+    # which the default (refined) solve then brings to FP64 level
+    p = pg.tb_supercell((3, 3, 3), seed=6)
+    sigma = -20.0                                   # below the spectrum: A - sigma B is SPD
+    note(f"fp32 unrefined solve n={p.n}")
+    P = K.Pencil.from_pencilgen(ctx, p)
+    F = P.factor(sigma, K.KTH_FP32_IR)
+    M = (p.A() - sigma * p.B()).tocsr()
+    b = np.random.default_rng(7).normal(size=p.n)
+    x1 = F.solve(b, refine=False)
+    x2 = F.solve(b)
+    b1, b2 = _berr(M, x1, b), _berr(M, x2, b)
+    note(f"  berr unrefined {b1:.2e}, refined {b2:.2e}")
+    assert 1e-12 < b1 < 1e-4
+    assert b2 <= 2e-15
