@@ -48,8 +48,12 @@ constexpr int kSolveChunk = 256;
 constexpr int kSolveRows = 256;
 // Schur-update output tile.
 constexpr int kTile = 64;
-// depth segment of a split left-looking update
+// depth segment of a split left-looking update of the rows below a pivot tile
 constexpr int kSegK = 256;
+// the diagonal block's update (one output tile per front, on the critical path)
+// takes segments of at least kSegKDiag columns, at most kMaxSegDiag of them
+constexpr int kSegKDiag = 32;
+constexpr int kMaxSegDiag = 64;
 
 struct Int2 { int32_t a, b; };
 
@@ -91,12 +95,12 @@ void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int
 // pivot tile t for tasks (front, first row) -- mode 0 the tile's diagonal block,
 // mode 1 rows below it; mode 2, tasks (front, lower tile number) of the
 // contribution block with depth ns.
-// Modes 0 / 1 with nseg > 1 split the depth into segments of kSegK whose partial
-// products go to part (bt.sP elements per batch: count * nseg * kTile^2 needed);
-// launch_gemm_reduce then applies them.
+// Modes 0 / 1 with nseg > 1 split the depth into segments of segk columns (a
+// multiple of 16) whose partial products go to part (bt.sP elements per batch:
+// count * nseg * kTile^2 needed); launch_gemm_reduce then applies them.
 template <typename T>
 void launch_gemm_lt(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int mode,
-                    int nseg, const Batch& bt, int nb, T* L, T* U, const T* W, T* part,
+                    int nseg, int segk, const Batch& bt, int nb, T* L, T* U, const T* W, T* part,
                     hipStream_t s);
 template <typename T>
 void launch_gemm_reduce(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int nseg,

@@ -191,10 +191,19 @@ static void build_schedule(Pencil& P) {
           for (int64_t r = t * kNB + kTile; r < S.nf(s); r += kTile) { sched.push_back(s); sched.push_back((int32_t)r); }
         }
       sp.ll_rest_cnt = (int32_t)((sched.size() - sp.ll_rest_off) / 2);
-      sp.ll_nseg = std::max<int32_t>(1, (int32_t)((t * kNB + kSegK - 1) / kSegK));
+      // depth t * kNB: kSegK-deep segments for the rows below; shorter ones for the
+      // diagonal block (its update precedes the tile factorization), at least
+      // kSegKDiag deep and at most kMaxSegDiag of them (the ordered reduction
+      // reads each)
+      const int64_t depth = (int64_t)t * kNB;
+      sp.ll_nseg = std::max<int32_t>(1, (int32_t)((depth + kSegK - 1) / kSegK));
+      sp.ll_segk_d = (int32_t)std::max<int64_t>(
+          kSegKDiag, ((depth + kMaxSegDiag - 1) / kMaxSegDiag + 15) / 16 * 16);
+      sp.ll_nseg_d = std::max<int32_t>(1, (int32_t)((depth + sp.ll_segk_d - 1) / sp.ll_segk_d));
       if (sp.ll_nseg > 1)
-        P.psize = std::max<int64_t>(P.psize, (int64_t)std::max(sp.ll_diag_cnt, sp.ll_rest_cnt) *
-                                                 sp.ll_nseg * kTile * kTile);
+        P.psize = std::max<int64_t>(P.psize, (int64_t)sp.ll_rest_cnt * sp.ll_nseg * kTile * kTile);
+      if (sp.ll_nseg_d > 1)
+        P.psize = std::max<int64_t>(P.psize, (int64_t)sp.ll_diag_cnt * sp.ll_nseg_d * kTile * kTile);
       lp.steps.push_back(sp);
     }
     // contribution blocks: lower kTile x kTile tiles of each nu x nu block (depth ns)
@@ -607,11 +616,12 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
         const Int2* rtask = reinterpret_cast<const Int2*>(sched + nx.ll_rest_off);
         {
           ProfScope ps(prof, st, PROF_GEMM, cn.lld, cn.lld_bytes);
-          launch_gemm_lt(P.meta, dtask, nx.ll_diag_cnt, nx.t, 0, nx.ll_nseg, bt, nb, Lf, Uf, Wf, Pf, st);
+          launch_gemm_lt(P.meta, dtask, nx.ll_diag_cnt, nx.t, 0, nx.ll_nseg_d, nx.ll_segk_d, bt, nb, Lf, Uf,
+                         Wf, Pf, st);
         }
-        if (nx.ll_nseg > 1) {
+        if (nx.ll_nseg_d > 1) {
           ProfScope ps(prof, st, PROF_REDUCE, 0.0);
-          launch_gemm_reduce(P.meta, dtask, nx.ll_diag_cnt, nx.t, nx.ll_nseg, bt, nb, Lf, Pf, st);
+          launch_gemm_reduce(P.meta, dtask, nx.ll_diag_cnt, nx.t, nx.ll_nseg_d, bt, nb, Lf, Pf, st);
         }
         KTH_HIP(hipEventRecord(c->ev_diag, st));
         KTH_HIP(hipStreamWaitEvent(c->aux, c->ev_diag, 0));
@@ -623,7 +633,8 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
         KTH_HIP(hipEventRecord(c->ev_tile, c->aux));
         {
           ProfScope ps(prof, st, PROF_GEMM, cn.ll, cn.ll_bytes);
-          launch_gemm_lt(P.meta, rtask, nx.ll_rest_cnt, nx.t, 1, nx.ll_nseg, bt, nb, Lf, Uf, Wf, Pf, st);
+          launch_gemm_lt(P.meta, rtask, nx.ll_rest_cnt, nx.t, 1, nx.ll_nseg, kSegK, bt, nb, Lf, Uf, Wf, Pf,
+                         st);
         }
         if (nx.ll_nseg > 1 && nx.ll_rest_cnt > 0) {
           ProfScope ps(prof, st, PROF_REDUCE, 0.0);
@@ -641,8 +652,8 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
           by_cb += 16.0 * nu * (nu + 1) / 2 + 2.0 * 8.0 * ns * nu;   // C once; L_u and W_u once
         }
       ProfScope ps(prof, st, PROF_GEMM, fl_cb, by_cb);
-      launch_gemm_lt(P.meta, reinterpret_cast<const Int2*>(sched + lp.cb_off), lp.cb_cnt, 0, 2, 1, bt,
-                     nb, Lf, Uf, Wf, Pf, st);
+      launch_gemm_lt(P.meta, reinterpret_cast<const Int2*>(sched + lp.cb_off), lp.cb_cnt, 0, 2, 1, 0,
+                     bt, nb, Lf, Uf, Wf, Pf, st);
     }
   }
   KTH_HIP(hipGetLastError());

@@ -840,12 +840,12 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
 // loads are in flight while the current one feeds the matrix cores.
 // ---------------------------------------------------------------------------
 // Split depth (modes 0 / 1, nseg > 1): workgroup g takes output tile g / nseg and
-// the depth segment [seg * kSegK, (seg + 1) * kSegK) with seg = g % nseg, and
+// the depth segment [seg * segk, (seg + 1) * segk) with seg = g % nseg, and
 // stores its product in part[g] (kTile x kTile); k_gemm_reduce adds the segments
 // in order and applies them.
 template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, int t, int mode,
-                                                int nseg, Batch bt, T* L, T* U, const T* W,
+                                                int nseg, int segk, Batch bt, T* L, T* U, const T* W,
                                                 T* part) {
   {
     const int64_t bidx = blockIdx.y;
@@ -870,7 +870,7 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
   if (mode < 2) {
     const int k0 = t * kNB, kb = min(kNB, f.ns - k0);
     ia = tk.b; ie = min(ia + kTile, f.nf); ja = k0; je = k0 + kb; K = k0;
-    if (nseg > 1) { Kb = seg * kSegK; K = min(K, Kb + kSegK); }
+    if (nseg > 1) { Kb = seg * segk; K = min(K, Kb + segk); }
     tri = (ia == k0);
     Cb = f.Lp + ia + (int64_t)ja * f.nf; ldc = f.nf;
   } else {
@@ -1088,12 +1088,12 @@ void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int
 
 template <typename T>
 void launch_gemm_lt(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int mode,
-                    int nseg, const Batch& bt, int nb, T* L, T* U, const T* W, T* part,
+                    int nseg, int segk, const Batch& bt, int nb, T* L, T* U, const T* W, T* part,
                     hipStream_t s) {
   if (count <= 0) return;
   if (mode == 2) nseg = 1;
   hipLaunchKernelGGL((k_gemm_lt<256, T>), dim3(count * nseg, nb), dim3(256), 0, s, M, tasks, t, mode,
-                     nseg, bt, L, U, W, part);
+                     nseg, segk, bt, L, U, W, part);
 }
 
 template <typename T>
@@ -1116,7 +1116,7 @@ void launch_gemm_reduce(const FrontMeta& M, const Int2* tasks, int32_t count, in
   template void launch_panel_trsm<T>(const FrontMeta&, const Int2*, int32_t, int32_t, const Batch&, \
                                      int, T*, T*, const double*, const double*, const int32_t*,     \
                                      const T*, FactStats*, hipStream_t);                            \
-  template void launch_gemm_lt<T>(const FrontMeta&, const Int2*, int32_t, int32_t, int, int,         \
+  template void launch_gemm_lt<T>(const FrontMeta&, const Int2*, int32_t, int32_t, int, int, int,    \
                                   const Batch&, int, T*, T*, const T*, T*, hipStream_t);            \
   template void launch_gemm_reduce<T>(const FrontMeta&, const Int2*, int32_t, int32_t, int,         \
                                       const Batch&, int, T*, const T*, hipStream_t);
