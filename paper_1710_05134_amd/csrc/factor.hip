@@ -9,7 +9,7 @@
 //   * larger fronts: k_front_init assembles column chunks in HBM (each entry
 //     written once: children's contributions gathered through inverse maps, then
 //     the original entries added); then per pivot tile of kNB columns:
-//     k_tile_factor (Bunch-Kaufman inside the tile, in LDS), k_panel_trsm (rows
+//     k_tile_factor (Bunch-Kaufman inside the tile), k_panel_trsm (rows
 //     below the tile: L21 = S21 P^T L11^{-T} D^{-1}, and W = L21 D kept
 //     panel-shaped); the column block of each tile is first brought up to date
 //     left-looking, C -= L(:, <k0) W(tile rows, <k0)^T on FP64 MFMA (k_gemm_lt),
@@ -330,33 +330,78 @@ __device__ inline void tile_sym_swap(T* F, T* Lo, int ld, int kb, int k, int a, 
   }
 }
 
-// Bunch-Kaufman LDL^T of one kb x kb pivot tile (kb <= kNB) in LDS by 4 wavefronts.
-// Every wave finds the pivot itself (lanes = rows, DPP maxima), so the decision
-// needs no broadcast; lane i of wave w forms row i's multipliers and updates the
-// columns j = w (mod 4) of row i.  Multipliers go to Lo (zeroed here; strictly
-// below the diagonal, 0 inside 2x2 blocks); F keeps the unscaled trailing matrix.
-// Two barriers per pivot step (after the search, after the update), three with an
-// interchange.
+// Bunch-Kaufman LDL^T of one kb x kb pivot tile (kb <= kNB) by 4 wavefronts with
+// the trailing matrix in registers: lane i of wave w holds row i's entries in the
+// columns j = 4m + w, R[m] (m = 0..15, static indices; entries above the diagonal
+// are not kept meaningful and never read).  Per pivot step the waves owning
+// columns k and k + 1 publish them (rows below the pivot, zero elsewhere) to an
+// LDS buffer of the step's parity; after one barrier every wave finds the pivot
+// itself from that column (lanes = rows, DPP maxima) and updates its registers
+// with 16 independent broadcast reads of it.  When the search must look at row r
+// (gamma_r), the registers are written to F (the tile in LDS, lower triangle as
+// the LDS formulation keeps it), searched and, for an interchange, permuted there
+// and loaded back.  The pivot rule and the rounding are those of the plain
+// column-by-column algorithm: every entry F(i, j), k < j <= i, receives one fused
+// multiply-add per pivot step, in step order.  Multipliers go to Lo (strictly
+// below the diagonal, 0 inside 2x2 blocks; zeroed here), interchanges to lp, the
+// block diagonal to d, e.
+// A row's kNB / 4 register entries as one vector: an element picked by a
+// wave-uniform index is read through indirect register addressing.
+template <typename T> struct RowRegs { typedef T type __attribute__((ext_vector_type(kNB / 4))); };
+
+// Columns k and k + 1 of the registers, published by the waves that own them:
+// yb[0][i] = F(i, k) for k < i < kb, yb[1][i] = F(i, k + 1) for k + 1 < i < kb (zero
+// elsewhere); pv = F(k, k), F(k + 1, k), F(k + 1, k + 1).
 template <typename T>
-__device__ void bk_tile_lds(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, BKCounts& cnt) {
+__device__ __forceinline__ void bk_publish(const typename RowRegs<T>::type& R, T (&yb)[2][kNB],
+                                           T (&pv)[3], int k, int kb, int wave, int i) {
+  if (wave == (k & 3)) {
+    const T v = R[k >> 2];
+    yb[0][i] = (i > k && i < kb) ? v : (T)0.0;
+    if (i == k) pv[0] = v;
+    if (i == k + 1) pv[1] = v;
+  }
+  if (k + 1 < kb && wave == ((k + 1) & 3)) {
+    const T v = R[(k + 1) >> 2];
+    yb[1][i] = (i > k + 1 && i < kb) ? v : (T)0.0;
+    if (i == k + 1) pv[2] = v;
+  }
+}
+
+template <typename T>
+__device__ void bk_tile_regs(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, BKCounts& cnt) {
+  constexpr int NM = kNB / 4;
+  __shared__ T yb[2][2][kNB];   // [parity][column k, column k + 1][row]
+  __shared__ T pv[2][3];        // [parity]: F(k, k), F(k + 1, k), F(k + 1, k + 1)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane;
   double maxl = 0.0;
   if (tid < kNB) lp[tid] = tid;
   for (int x = tid; x < kNB * kNB; x += blockDim.x) Lo[(x & 63) + (x >> 6) * ld] = 0.0;
-  __syncthreads();
-  int k = 0;
+  typename RowRegs<T>::type R;
+#pragma unroll
+  for (int m = 0; m < NM; m++) {
+    const int j = 4 * m + wave;
+    R[m] = (j <= i && i < kb) ? F[i + j * ld] : (T)0.0;
+  }
+  int k = 0, par = 0;
   while (k < kb) {
+    bk_publish<T>(R, yb[par], pv[par], k, kb, wave, i);
+    __syncthreads();
     // gamma_1 and its row r among the candidates k < i < kb (ties: smallest row)
+    const T ck = yb[par][0][i];
     unsigned long long key = 0;
-    if (i > k && i < kb)
-      key = (dbits(fabs((double)F[i + k * ld])) & ~0xFFull) | (unsigned long long)(128 - i);
+    if (i > k && i < kb) key = (dbits(fabs((double)ck)) & ~0xFFull) | (unsigned long long)(128 - i);
     key = wave_max_u64(key);
     const int r = key == 0 ? k : 128 - (int)(key & 0xFFull);
-    const double g1 = key == 0 ? 0.0 : fabs((double)F[r + k * ld]);
-    const double akk = fabs((double)F[k + k * ld]);
+    const double g1 = key == 0 ? 0.0 : fabs((double)yb[par][0][r]);
+    const double akk = fabs((double)pv[par][0]);
     int kind = 0;
     if (!(g1 == 0.0 || akk >= kAlphaBK * g1)) {
+      // row and column r: through the tile in LDS
+#pragma unroll
+      for (int m = 0; m < NM; m++) F[i + (4 * m + wave) * ld] = R[m];
+      __syncthreads();
       unsigned long long gb = 0;   // |.| >= 0: bit patterns order as the values
       if (i >= k && i < kb && i != r)
         gb = dbits(i < r ? fabs((double)F[r + i * ld]) : fabs((double)F[i + r * ld]));
@@ -364,31 +409,38 @@ __device__ void bk_tile_lds(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, BK
       if (akk * gr >= kAlphaBK * g1 * g1) kind = 0;
       else if (fabs((double)F[r + r * ld]) >= kAlphaBK * gr) kind = 1;
       else kind = 2;
-    }
-    // every wave has finished its search reads before any entry moves or changes
-    __syncthreads();
-    if (kind == 1 || (kind == 2 && r != k + 1)) {
-      const int a = kind == 1 ? k : k + 1;
-      tile_sym_swap<T>(F, Lo, ld, kb, k, a, r);
-      if (tid == 0) { int t = lp[a]; lp[a] = lp[r]; lp[r] = t; }
-      __syncthreads();
+      if (kind == 1 || (kind == 2 && r != k + 1)) {
+        const int a = kind == 1 ? k : k + 1;
+        __syncthreads();   // every wave has read row r
+        tile_sym_swap<T>(F, Lo, ld, kb, k, a, r);
+        if (tid == 0) { int t = lp[a]; lp[a] = lp[r]; lp[r] = t; }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < NM; m++) R[m] = F[i + (4 * m + wave) * ld];
+        bk_publish<T>(R, yb[par ^ 1], pv[par ^ 1], k, kb, wave, i);   // interchanged, other buffer
+        __syncthreads();
+        par ^= 1;
+      }
     }
     if (kind < 2) {
-      const T dk = F[k + k * ld];
+      const T dk = pv[par][0];
       if (tid == 0) {
         d[k] = dk; e[k] = 0.0;
         if (dk < 0) cnt.neg++; else if (dk > 0) cnt.pos++; else cnt.zero++;
         cnt.mind = fmin(cnt.mind, fabs((double)dk));
       }
-      if (dk != 0.0 && i > k && i < kb) {
-        const T li = F[i + k * ld] / dk;
-        for (int j = k + 1 + wave; j <= i; j += 4) F[i + j * ld] -= li * F[j + k * ld];
-        if (wave == 0) { Lo[i + k * ld] = li; maxl = fmax(maxl, fabs((double)li)); }
+      if (dk != 0.0) {
+        const bool act = i > k && i < kb;
+        const T li = act ? yb[par][0][i] / dk : (T)0.0;
+        // rows k < i < kb, columns k < j <= i: column k is zero outside k < j < kb, li
+        // outside k < i < kb; entries above the diagonal take values never read
+#pragma unroll
+        for (int m = 0; m < NM; m++) R[m] = R[m] - li * yb[par][0][4 * m + wave];
+        if (wave == 0 && act) { Lo[i + k * ld] = li; maxl = fmax(maxl, fabs((double)li)); }
       }
-      __syncthreads();
       k += 1;
     } else {
-      const T a = F[k + k * ld], b = F[(k + 1) + k * ld], c = F[(k + 1) + (k + 1) * ld];
+      const T a = pv[par][0], b = pv[par][1], c = pv[par][2];
       const T det = a * c - b * b;
       if (tid == 0) {
         d[k] = a; e[k] = b; d[k + 1] = c; e[k + 1] = 0.0;
@@ -400,20 +452,28 @@ __device__ void bk_tile_lds(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, BK
         const T m = 0.5 * tr, q = sqrt(0.25 * (a - c) * (a - c) + b * b);
         cnt.mind = fmin(cnt.mind, fmin(fabs((double)m - q), fabs((double)m + q)));
       }
-      if (i > k + 1 && i < kb) {
-        const T w1 = F[i + k * ld], w2 = F[i + (k + 1) * ld];
-        const T l1 = (c * w1 - b * w2) / det, l2 = (a * w2 - b * w1) / det;
-        for (int j = k + 2 + wave; j <= i; j += 4)
-          F[i + j * ld] -= l1 * F[j + k * ld] + l2 * F[j + (k + 1) * ld];
-        if (wave == 0) {
-          Lo[i + k * ld] = l1;
-          Lo[i + (k + 1) * ld] = l2;
-          maxl = fmax(maxl, fmax(fabs((double)l1), fabs((double)l2)));
-        }
+      const bool act = i > k + 1 && i < kb;
+      T l1 = 0.0, l2 = 0.0;
+      if (act) {
+        const T w1 = yb[par][0][i], w2 = yb[par][1][i];
+        l1 = (c * w1 - b * w2) / det;
+        l2 = (a * w2 - b * w1) / det;
       }
-      __syncthreads();
+      // columns j > k + 1 only: column k's entry F(k + 1, k) is masked here
+#pragma unroll
+      for (int m = 0; m < NM; m++) {
+        const int j = 4 * m + wave;
+        const T u1 = j > k + 1 ? yb[par][0][j] : (T)0.0;
+        R[m] = R[m] - (l1 * u1 + l2 * yb[par][1][j]);
+      }
+      if (wave == 0 && act) {
+        Lo[i + k * ld] = l1;
+        Lo[i + (k + 1) * ld] = l2;
+        maxl = fmax(maxl, fmax(fabs((double)l1), fabs((double)l2)));
+      }
       k += 2;
     }
+    par ^= 1;
   }
   if (wave == 0) {
     for (int off = 32; off > 0; off >>= 1) maxl = fmax(maxl, __shfl_xor(maxl, off));
@@ -633,7 +693,7 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
   }
   __syncthreads();
   BKCounts cnt{0, 0, 0, 0, INFINITY, 0.0};
-  bk_tile_lds<T>(Tl, Lo, LD, kb, lp, dd, ee, cnt);
+  bk_tile_regs<T>(Tl, Lo, LD, kb, lp, dd, ee, cnt);
   // unit-lower L_tt back to the panel (ones on the diagonal, zeros inside 2x2 blocks)
   for (int x0 = 0; x0 < kb * kb; x0 += NT * U) {
     T v[U];
