@@ -338,9 +338,9 @@ __device__ inline void tile_sym_swap(T* F, T* Lo, int ld, int kb, int k, int a, 
 // LDS buffer of the step's parity; after one barrier every wave finds the pivot
 // itself from that column (lanes = rows, DPP maxima) and updates its registers
 // with 16 independent broadcast reads of it.  When the search must look at row r
-// (gamma_r), the registers are written to F (the tile in LDS, lower triangle as
-// the LDS formulation keeps it), searched and, for an interchange, permuted there
-// and loaded back.  The pivot rule and the rounding are those of the plain
+// (gamma_r), the registers are written to F (the tile in LDS; only its lower
+// triangle is read), searched and, for an interchange, permuted there and loaded
+// back.  The pivot rule and the rounding are those of the plain
 // column-by-column algorithm: every entry F(i, j), k < j <= i, receives one fused
 // multiply-add per pivot step, in step order.  Multipliers go to Lo (strictly
 // below the diagonal, 0 inside 2x2 blocks; zeroed here), interchanges to lp, the
