@@ -661,17 +661,6 @@ struct ND {
         best_sep = W[2]; best_imb = imb; part = trial;
       }
     }
-#ifdef KTH_DEBUG_ND
-    {
-      int64_t bad = 0, ns = 0, n0 = 0, n1 = 0;
-      for (int32_t v = 0; v < w.n; v++) {
-        if (part[v] == 2) ns++; else if (part[v] == 0) n0++; else n1++;
-        for (int64_t e = w.xadj[v]; e < w.xadj[v + 1]; e++)
-          if (part[v] + part[w.adj[e]] == 1) bad++;
-      }
-      if (w.n > 2000) fprintf(stderr, "nd n=%d sep=%ld p0=%ld p1=%ld bad=%ld\n", w.n, ns, n0, n1, bad);
-    }
-#endif
     std::vector<int32_t> P0, P1, S;
     for (int32_t i = 0; i < w.n; i++) (part[i] == 0 ? P0 : part[i] == 1 ? P1 : S).push_back(V[i]);
     for (int32_t v : V) local[v] = -1;
