@@ -176,3 +176,30 @@ def test_fp32_unrefined_solve(K, ctx):
     note(f"  berr unrefined {b1:.2e}, refined {b2:.2e}")
     assert 1e-12 < b1 < 1e-4
     assert b2 <= 2e-15
+
+
+def test_eig_fp32_n524k_matches_fp64(K, ctx):
+    # the precision workload: n = 524288, k = n/2, inertia factorizations in FP64,
+    # the shift-and-invert factor in FP32 with FP64 refinement of every solve;
+    # lambda_k and the residual against the FP64 path, and the inertia bracket
+    p = pg.workload("n524k")
+    sv = pg.start_vectors(p.n)
+    note(f"eig fp32 SI n={p.n} k={p.k}")
+    P = K.Pencil.from_pencilgen(ctx, p)
+    lam64, x64, i64 = P.eig(p.k, start_vectors=sv)
+    lam32, x32, i32 = P.eig(p.k, start_vectors=sv, si_precision=K.KTH_FP32_IR)
+    nA = od.norm_inf(p)
+    A, B = p.A(), p.B()
+    res32 = np.linalg.norm(A @ x32 - lam32 * (B @ x32)) / (nA * np.linalg.norm(x32))
+    res64 = np.linalg.norm(A @ x64 - lam64 * (B @ x64)) / (nA * np.linalg.norm(x64))
+    note(f"  lambda fp64 {lam64!r} fp32+IR {lam32!r} (|diff| {abs(lam32 - lam64):.2e}); residual "
+         f"fp32+IR {res32:.2e} fp64 {res64:.2e}; ir_steps {i32['ir_steps']} over {i32['si_steps']} solves, "
+         f"max berr {i32['ir_max_berr']:.2e}, fallback {i32['ir_fallback']}")
+    assert i32["k_validated"] == p.k and i64["k_validated"] == p.k
+    assert i32["si_precision"] == K.KTH_FP32_IR and i32["ir_fallback"] == 0
+    assert i32["ir_max_berr"] <= 1e-14
+    assert abs(lam32 - lam64) <= 1e-10 * nA
+    assert res32 <= 1e-9 and res64 <= 1e-9
+    assert abs(x32 @ (B @ x64)) >= 1 - 1e-8            # the same B-normalised vector
+    d = 1e-10 * nA
+    assert P.nu(lam32 - d) < p.k <= P.nu(lam32 + d)
