@@ -263,12 +263,15 @@ __global__ __launch_bounds__(kFwdThreads) void k_lfwd_step(FrontMeta M, const In
 #pragma unroll
     for (int q = 0; q < kNB; q++) Lv[q] = q < kb ? Lv[q] : 0.0;
   }
+  // this row's right-hand side, read before the barrier: rows below the tile are
+  // written by their own workgroup only
+  const double ri = (tid >= 64 && i < nf) ? Rs[i] : 0.0;
   __syncthreads();
   if (tid >= 64 && i < nf) {
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < kNB; q++) acc = fma(Lv[q], z[q], acc);
-    Rs[i] -= acc;
+    Rs[i] = ri - acc;
   }
   if (r0 == k0 + kb && tid < kb) ye[f0 + k0 + tid] = apply_dinv(D, E, z, f0 + k0 + tid, tid, kb);
 }
@@ -342,15 +345,20 @@ __global__ __launch_bounds__(kBwdThreads) void k_lbwd_step(FrontMeta M, const In
   const int k0 = t * kNB, kb = min(kNB, ns - k0);
   const int rb = k0 + kb;                      // first row below the tile
   const int64_t pb = pbase[s];
-  if (r0 == rb && rb < ns)                     // tile t+1 exists and opens this chunk
-    bwd_finish_tile(M, s, t + 1, L, tperm, ye, partial + (((t + 1) & 1) * half + pb) * kNB, xe, tl);
-  const T* Lp = L + M.lptr[s];
   const int i = r0 + tid;
+  const int ic = min(i, nf - 1);
+  const int64_t gi = M.rows[M.rptr[s] + ic];
+  // tile t+1 exists and opens this chunk: this workgroup finishes it first; x of
+  // its rows is ready after that, x of every other row already
+  const bool fin = r0 == rb && rb < ns;
+  const bool late = fin && i < min(rb + kNB, ns);
+  double xi = (!late && i < nf) ? xe[gi] : 0.0;
+  if (fin) bwd_finish_tile(M, s, t + 1, L, tperm, ye, partial + (((t + 1) & 1) * half + pb) * kNB, xe, tl);
+  if (late) xi = xe[gi];
+  const T* Lp = L + M.lptr[s];
   {
     // unconditional loads from clamped (valid) addresses, masked afterwards, so
     // that all 64 are in flight together
-    const int ic = min(i, nf - 1);
-    const double xi = i < nf ? xe[M.rows[M.rptr[s] + ic]] : 0.0;
     double v[kNB];
 #pragma unroll
     for (int q = 0; q < kNB; q++) v[q] = (double)Lp[ic + (int64_t)(k0 + min(q, kb - 1)) * nf];
