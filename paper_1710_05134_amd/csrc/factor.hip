@@ -777,6 +777,54 @@ template <> struct MF<float> {
   __device__ static inline int mrow(int r, int lane) { return 4 * (lane >> 4) + r; }
 };
 
+// s_waitcnt immediate that waits for the vector-memory counter to reach n (the
+// LDS and export counters are left alone): vmcnt bits [3:0] and [15:14].
+__device__ constexpr int vmcnt_imm(int n) {
+  return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8);
+}
+
+// The 16 operand values of one depth chunk of k_gemm_lt: av[s][a] at byte
+// address ba + a * 16 rows + s * 4 columns, bv likewise from bb (LDS, column
+// stride kTile).  One asm block issues the 16 reads and waits for them.
+__device__ __forceinline__ void lds_read_chunk(uint32_t ba, uint32_t bb, double (&av)[4][2],
+                                               double (&bv)[4][2]) {
+  asm volatile(
+      "ds_read_b64 %0, %16\n ds_read_b64 %1, %16 offset:128\n"
+      "ds_read_b64 %2, %16 offset:2048\n ds_read_b64 %3, %16 offset:2176\n"
+      "ds_read_b64 %4, %16 offset:4096\n ds_read_b64 %5, %16 offset:4224\n"
+      "ds_read_b64 %6, %16 offset:6144\n ds_read_b64 %7, %16 offset:6272\n"
+      "ds_read_b64 %8, %17\n ds_read_b64 %9, %17 offset:128\n"
+      "ds_read_b64 %10, %17 offset:2048\n ds_read_b64 %11, %17 offset:2176\n"
+      "ds_read_b64 %12, %17 offset:4096\n ds_read_b64 %13, %17 offset:4224\n"
+      "ds_read_b64 %14, %17 offset:6144\n ds_read_b64 %15, %17 offset:6272\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(av[0][0]), "=&v"(av[0][1]), "=&v"(av[1][0]), "=&v"(av[1][1]), "=&v"(av[2][0]),
+        "=&v"(av[2][1]), "=&v"(av[3][0]), "=&v"(av[3][1]), "=&v"(bv[0][0]), "=&v"(bv[0][1]),
+        "=&v"(bv[1][0]), "=&v"(bv[1][1]), "=&v"(bv[2][0]), "=&v"(bv[2][1]), "=&v"(bv[3][0]),
+        "=&v"(bv[3][1])
+      : "v"(ba), "v"(bb)
+      : "memory");
+}
+__device__ __forceinline__ void lds_read_chunk(uint32_t ba, uint32_t bb, float (&av)[4][2],
+                                               float (&bv)[4][2]) {
+  asm volatile(
+      "ds_read_b32 %0, %16\n ds_read_b32 %1, %16 offset:64\n"
+      "ds_read_b32 %2, %16 offset:1024\n ds_read_b32 %3, %16 offset:1088\n"
+      "ds_read_b32 %4, %16 offset:2048\n ds_read_b32 %5, %16 offset:2112\n"
+      "ds_read_b32 %6, %16 offset:3072\n ds_read_b32 %7, %16 offset:3136\n"
+      "ds_read_b32 %8, %17\n ds_read_b32 %9, %17 offset:64\n"
+      "ds_read_b32 %10, %17 offset:1024\n ds_read_b32 %11, %17 offset:1088\n"
+      "ds_read_b32 %12, %17 offset:2048\n ds_read_b32 %13, %17 offset:2112\n"
+      "ds_read_b32 %14, %17 offset:3072\n ds_read_b32 %15, %17 offset:3136\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(av[0][0]), "=&v"(av[0][1]), "=&v"(av[1][0]), "=&v"(av[1][1]), "=&v"(av[2][0]),
+        "=&v"(av[2][1]), "=&v"(av[3][0]), "=&v"(av[3][1]), "=&v"(bv[0][0]), "=&v"(bv[0][1]),
+        "=&v"(bv[1][0]), "=&v"(bv[1][1]), "=&v"(bv[2][0]), "=&v"(bv[2][1]), "=&v"(bv[3][0]),
+        "=&v"(bv[3][1])
+      : "v"(ba), "v"(bb)
+      : "memory");
+}
+
 // ---------------------------------------------------------------------------
 // Large fronts: rows below pivot tile t, 64 rows per workgroup.
 //   W = S P^T L_tt^{-T}  (MFMA, with the tile inverse from k_tile_factor)
@@ -913,8 +961,10 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
     part += bidx * bt.sP;
   }
   constexpr int KC = 16;         // depth chunk staged through LDS
-  __shared__ T As[kTile * KC];   // A rows (i) x q, ld kTile
-  __shared__ T Bs[kTile * KC];   // B rows (j) x q, ld kTile
+  // three chunk buffers per operand (rows x q, ld kTile), filled by direct
+  // global-to-LDS loads two chunks ahead of the one being multiplied
+  __shared__ T A0[kTile * KC], A1[kTile * KC], A2[kTile * KC];
+  __shared__ T B0[kTile * KC], B1[kTile * KC], B2[kTile * KC];
   const int g = blockIdx.x;
   const int seg = g % nseg;
   const Int2 tk = tasks[g / nseg];
@@ -955,48 +1005,78 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
   for (int a = 0; a < 2; a++)
 #pragma unroll
     for (int b = 0; b < 2; b++) acc[a][b] = MF<T>::zero();
-  // operand staging: thread = (row r = tid % 64, column residue c = tid / 64); rows
-  // beyond the tile are clamped (they only feed outputs that are not written),
-  // columns beyond the depth are zeroed
-  constexpr int UL = kTile * KC / NT;    // loads of each operand per thread and chunk
-  const int r = tid & 63, c4 = tid >> 6;
-  const T* pA = Lp + min(ia + r, ie - 1);
-  const T* pB = Wp + min(ja + r, je - 1);
-  T va[UL], vb[UL];
-  auto load = [&](int q0) {
+  // operand staging: each wave moves 4-byte pieces of its share of the chunk's
+  // columns straight into LDS (lane l: piece l % EPL of row h * RPI + l / EPL);
+  // rows beyond the tile are clamped (they only feed outputs that are not
+  // written), columns beyond the depth are clamped and then zeroed in LDS
+  constexpr int EPL = sizeof(T) / 4;        // 4-byte pieces per element
+  constexpr int RPI = kTile / EPL;          // rows per load instruction
+  constexpr int IPW = KC * EPL / (NT / 64); // load instructions per operand and wave
+  static_assert(NT == 256 && kTile == 64, "four waves, 64-row tiles");
+  const int nch = (K - Kb + KC - 1) / KC;
+  auto issue = [&](int ch, T* Ab, T* Bb) {
+    const int q0 = Kb + ch * KC;
 #pragma unroll
-    for (int u = 0; u < UL; u++) {
-      const int q = q0 + c4 + 4 * u;
-      const int64_t off = (int64_t)min(q, K - 1) * f.nf;
-      va[u] = pA[off];
-      vb[u] = pB[off];
-      if (q >= K) { va[u] = 0.0; vb[u] = 0.0; }
+    for (int u = 0; u < IPW; u++) {
+      const int idx = wave * IPW + u, c = idx / EPL, h = idx % EPL;
+      const int64_t q = min(q0 + c, K - 1);
+      const int row = h * RPI + lane / EPL;
+      const char* sa = reinterpret_cast<const char*>(Lp + min(ia + row, ie - 1) + q * f.nf) + 4 * (lane % EPL);
+      const char* sb = reinterpret_cast<const char*>(Wp + min(ja + row, je - 1) + q * f.nf) + 4 * (lane % EPL);
+      __builtin_amdgcn_global_load_lds(sa, (__attribute__((address_space(3))) void*)(Ab + c * kTile + h * RPI), 4, 0, 0);
+      __builtin_amdgcn_global_load_lds(sb, (__attribute__((address_space(3))) void*)(Bb + c * kTile + h * RPI), 4, 0, 0);
     }
   };
   const bool direct = nseg == 1;
-  if (K > Kb) load(Kb);
   const int m = lane & 15, kk = lane >> 4;
-  for (int q0 = Kb; q0 < K; q0 += KC) {
-    __syncthreads();   // the previous chunk has been consumed
+  // 16 operand values of a chunk (4 depth steps x 2 row blocks of A and of B), read
+  // in one block that waits for its own reads: the compiler does not see these
+  // LDS reads, so it adds no wait for the loads still filling the other buffers
+  const uint32_t offA = ((wr + m) + kk * kTile) * (uint32_t)sizeof(T);
+  const uint32_t offB = ((wc + m) + kk * kTile) * (uint32_t)sizeof(T);
+  auto mult = [&](const T* Ab, const T* Bb) {
+    typedef __attribute__((address_space(3))) T* lds_ptr;   // 32-bit LDS addresses
+    const uint32_t ba = (uint32_t)(uintptr_t)(lds_ptr)Ab + offA;
+    const uint32_t bb = (uint32_t)(uintptr_t)(lds_ptr)Bb + offB;
+    T av[4][2], bv[4][2];
+    lds_read_chunk(ba, bb, av, bv);
 #pragma unroll
-    for (int u = 0; u < UL; u++) {
-      As[r + (c4 + 4 * u) * kTile] = va[u];
-      Bs[r + (c4 + 4 * u) * kTile] = vb[u];
-    }
-    __syncthreads();
-    if (q0 + KC < K) load(q0 + KC);
-#pragma unroll
-    for (int qq = 0; qq < KC; qq += 4) {
-      T av[2], bv[2];
-#pragma unroll
-      for (int a = 0; a < 2; a++) av[a] = As[(wr + a * 16 + m) + (qq + kk) * kTile];
-#pragma unroll
-      for (int b = 0; b < 2; b++) bv[b] = Bs[(wc + b * 16 + m) + (qq + kk) * kTile];
+    for (int s4 = 0; s4 < 4; s4++)
       // D(m = j, n = i) = sum_q B(j, q) A(i, q)
 #pragma unroll
       for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int b = 0; b < 2; b++) acc[a][b] = MF<T>::step(bv[b], av[a], acc[a][b]);
+        for (int b = 0; b < 2; b++) acc[a][b] = MF<T>::step(bv[s4][b], av[s4][a], acc[a][b]);
+  };
+  // columns q >= K of the last chunk hold clamped copies: zero them
+  auto zero_tail = [&](int ch, T* Ab, T* Bb) {
+    const int cv = K - (Kb + ch * KC);
+    if (cv >= KC) return;
+    __syncthreads();
+    for (int x = tid; x < kTile * KC; x += NT)
+      if (x / kTile >= cv) { Ab[x] = 0.0; Bb[x] = 0.0; }
+    __syncthreads();
+  };
+  constexpr int W1 = IPW * 2;               // one chunk's loads per wave (A and B)
+  if (nch > 0) issue(0, A0, B0);
+  if (nch > 1) issue(1, A1, B1);
+  for (int ch = 0; ch < nch; ch += 3) {
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+      const int c = ch + v;
+      if (c >= nch) break;
+      T* Ab = v == 0 ? A0 : v == 1 ? A1 : A2;
+      T* Bb = v == 0 ? B0 : v == 1 ? B1 : B2;
+      // chunk c has landed in this wave's pieces (the next chunk's may still be in
+      // flight); after the barrier every wave's pieces have, and every wave is
+      // done with chunk c - 1, whose buffers chunk c + 2 refills
+      if (c + 1 < nch) __builtin_amdgcn_s_waitcnt(vmcnt_imm(W1));
+      else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      if (c == nch - 1) zero_tail(c, Ab, Bb);
+      if (c + 2 < nch) issue(c + 2, v == 0 ? A2 : v == 1 ? A0 : A1, v == 0 ? B2 : v == 1 ? B0 : B1);
+      mult(Ab, Bb);
     }
   }
   if (!direct) {
