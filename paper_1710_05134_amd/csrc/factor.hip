@@ -944,8 +944,9 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
 //   mode 2, the contribution block, lower 64 x 64 tile number b of it:
 //       U(i, j) -= sum_{q < ns} L(ns + i, q) W(ns + j, q),   i >= j
 // W = L D is kept panel-shaped (same offsets and ld as L) by k_panel_trsm.  The
-// depth is walked in chunks of kNB columns staged through LDS; the next chunk's
-// loads are in flight while the current one feeds the matrix cores.
+// depth is walked in chunks of 16 columns loaded straight from global memory into
+// three LDS buffers; the next two chunks' loads are in flight while the current
+// one feeds the matrix cores.
 // ---------------------------------------------------------------------------
 // Split depth (modes 0 / 1, nseg > 1): workgroup g takes output tile g / nseg and
 // the depth segment [seg * segk, (seg + 1) * segk) with seg = g % nseg, and
