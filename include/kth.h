@@ -127,6 +127,11 @@ kth_status kth_factor_inertia(kth_factor_t f, int64_t* neg, int64_t* zero, int64
 kth_status kth_solve(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr, double* x,
                      int64_t ldx, uint32_t flags);
 kth_status kth_factor_destroy(kth_factor_t f);
+/* Pivot statistics of a kept factor (FP64 or FP32): n2x2 = number of 2x2 blocks of
+ * D; min_pivot_rel = smallest |eigenvalue of a D block| / (||A||_inf + |sigma|
+ * ||B||_inf); max_abs_l = largest |L_ij| (element growth of the restricted
+ * Bunch-Kaufman pivoting, Section 2.1).  Any pointer may be NULL. */
+kth_status kth_factor_stats(kth_factor_t f, int64_t* n2x2, double* min_pivot_rel, double* max_abs_l);
 
 typedef struct {
   int64_t m_max;          /* bisection stops at <= m_max eigenvalues in the interval (20)    */
@@ -165,6 +170,12 @@ typedef struct {
   int32_t ir_steps;           /* FP32-factor applications spent on refinement (all SI solves)  */
   int32_t ir_fallback;        /* 1 if a stalled refinement switched the factor to FP64          */
   double ir_max_berr;         /* largest backward error at exit of a refined solve             */
+  double max_abs_l;           /* largest |L_ij| over the counted FP64 factorizations           */
+  int32_t weak_pivot_nudges;  /* shifts moved because a count was not trusted: a zero pivot, a
+                                 pivot below 1e-13 (||A||_inf + |sigma| ||B||_inf), or a
+                                 multiplier above 1e8 (restricted pivoting, Section 2.1)     */
+  int32_t weak_pivot_kept;    /* counts accepted with a weak nonzero pivot after three moves   */
+  int32_t stage1_restarts;    /* stage-1 Lanczos restarts after a breakdown (beta = 0)         */
 } kth_info;
 
 void kth_opts_default(kth_opts* o);
@@ -177,7 +188,10 @@ kth_status kth_eig(kth_pencil p, int64_t k, const kth_opts* opts, double* lambda
  * (opts->batch_workers) take the pencils in turn, each on streams of its own that
  * first wait for the work queued on the context stream; the call returns when all
  * are done.  per_pencil: np statuses (the call itself returns KTH_OK unless its
- * arguments are invalid); kth_last_error(ctx) holds one failing pencil's message. */
+ * arguments are invalid); kth_last_error(ctx) holds one failing pencil's message.
+ * Each pencil handle may appear once: a pencil owns the workspace of its runs, so
+ * a repeated handle is rejected with KTH_EINVAL before any work starts (run the
+ * same pencil for several k with successive kth_eig calls). */
 kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int64_t* k,
                          const kth_opts* opts, double* lambda, double* const* x, kth_info* info,
                          kth_status* per_pencil);

@@ -44,6 +44,19 @@ def eig(pencil):
     return lam, X
 
 
+def eigvals(pencil):
+    """All eigenvalues (ascending) by the same Cholesky reduction, without
+    eigenvectors (the symmetric eigenvalue-only driver)."""
+    A, B = densify(pencil)
+    try:
+        R = np.linalg.cholesky(B)
+    except np.linalg.LinAlgError as e:
+        raise NotPositiveDefinite(str(e))
+    Y = sla.solve_triangular(R, A, lower=True)
+    Cm = sla.solve_triangular(R, Y.T, lower=True).T
+    return np.linalg.eigvalsh(0.5 * (Cm + Cm.T))
+
+
 def sign_fix(x: np.ndarray) -> np.ndarray:
     """Largest-magnitude component made positive (first one on ties)."""
     i = int(np.argmax(np.abs(x)))

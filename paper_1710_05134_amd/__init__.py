@@ -53,7 +53,9 @@ class kth_info(C.Structure):
                 ("peak_device_bytes", C.c_double), ("n_sigmas", C.c_int32),
                 ("sigmas", C.c_double * 128), ("nus", C.c_int64 * 128),
                 ("si_precision", C.c_int32), ("ir_steps", C.c_int32), ("ir_fallback", C.c_int32),
-                ("ir_max_berr", C.c_double)]
+                ("ir_max_berr", C.c_double), ("max_abs_l", C.c_double),
+                ("weak_pivot_nudges", C.c_int32), ("weak_pivot_kept", C.c_int32),
+                ("stage1_restarts", C.c_int32)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -95,6 +97,7 @@ def lib() -> C.CDLL:
         "kth_factor_inertia": ([vp, p64, p64, p64], C.c_int),
         "kth_solve": ([vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, C.c_uint32], C.c_int),
         "kth_factor_destroy": ([vp], C.c_int),
+        "kth_factor_stats": ([vp, p64, pd, pd], C.c_int),
         "kth_opts_default": ([C.POINTER(kth_opts)], None),
         "kth_eig": ([vp, C.c_int64, C.POINTER(kth_opts), pd, pd, C.POINTER(kth_info)], C.c_int),
         "kth_eig_batch": ([vp, C.c_int32, C.POINTER(vp), p64, C.POINTER(kth_opts), pd,
@@ -274,6 +277,13 @@ class Factor:
         _check(lib().kth_factor_inertia(self.h, C.byref(a), C.byref(b), C.byref(c)),
                self.pencil.ctx.h)
         return a.value, b.value, c.value
+
+    def stats(self) -> dict:
+        """n2x2, min_pivot_rel, max_abs_l of the factor (see kth_factor_stats)."""
+        n2, md, ml = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().kth_factor_stats(self.h, C.byref(n2), C.byref(md), C.byref(ml)),
+               self.pencil.ctx.h)
+        return dict(n2x2=n2.value, min_pivot_rel=md.value, max_abs_l=ml.value)
 
     def solve(self, r, refine: bool = True):
         """X = (A - sigma B)^{-1} R; refine=False applies an FP32 factor once."""

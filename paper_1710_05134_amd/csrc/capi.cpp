@@ -2,6 +2,7 @@
 // converts exceptions into a kth_status and keeps the message on its context.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -312,6 +313,24 @@ kth_status kth_factor_destroy(kth_factor_t f) {
   return KTH_OK;
 }
 
+kth_status kth_factor_stats(kth_factor_t f, int64_t* n2x2, double* min_pivot_rel, double* max_abs_l) {
+  if (!f) return KTH_EINVAL;
+  if (!f->f.have_stats) {
+    f->pen->ctx->c.last_error = "factor has no statistics";
+    return KTH_ESTATE;
+  }
+  const FactStats& h = f->f.hs;
+  double md, ml;
+  std::memcpy(&md, &h.min_d_bits, sizeof(md));
+  std::memcpy(&ml, &h.max_l_bits, sizeof(ml));
+  const Pencil& P = f->pen->p;
+  const double scale = P.normA_inf + std::fabs(f->f.sigma) * P.normB_inf;
+  if (n2x2) *n2x2 = (int64_t)h.n2x2;
+  if (min_pivot_rel) *min_pivot_rel = scale > 0 ? md / scale : md;
+  if (max_abs_l) *max_abs_l = ml;
+  return KTH_OK;
+}
+
 void kth_opts_default(kth_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
@@ -357,6 +376,11 @@ kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int
       if (!p[i] || p[i]->ctx != ctx) throw Error(KTH_EINVAL, "pencil from another context");
       ps[i] = &p[i]->p;
     }
+    // a pencil's workspaces (scratch factor, update pool, panels) serve one run at a time
+    std::vector<Pencil*> sorted(ps);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      throw Error(KTH_EINVAL, "the same pencil appears more than once in the batch");
     eig_batch(ctx->c, ps, k, o, lambda, x, info, per_pencil);
   });
 }

@@ -139,18 +139,21 @@ double dot_dev(Work& W, const double* a, const double* b) {
   return r;
 }
 
-// nu(sigma) with the pencil's scratch factor; returns neg, sets zero count
-int64_t count_nu(Pencil& P, double sigma, int64_t* zero, double* mind) {
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, sizeof(d));
+  return d;
+}
+
+// nu(sigma) with the pencil's scratch factor; returns neg, sets the zero count,
+// min |pivot| and max |L_ij|
+int64_t count_nu(Pencil& P, double sigma, int64_t* zero, double* mind, double* maxl) {
   NumFactor& F = *P.scratch;
   factor_enqueue(P, F, sigma, false);
   factor_read_stats(P, F);
   if (zero) *zero = (int64_t)F.hs.zero;
-  if (mind) {
-    double md;
-    unsigned long long b = F.hs.min_d_bits;
-    std::memcpy(&md, &b, sizeof(md));
-    *mind = md;
-  }
+  if (mind) *mind = bits_to_double(F.hs.min_d_bits);
+  if (maxl) *maxl = bits_to_double(F.hs.max_l_bits);
   return (int64_t)F.hs.neg;
 }
 
@@ -158,22 +161,45 @@ struct Shifts {
   std::vector<double> s;
   std::vector<int64_t> nu;
   double min_pivot_rel = INFINITY;
+  double max_abs_l = 0;
+  int nudges = 0;      // shifts moved for a zero or weak pivot or large growth
+  int weak_kept = 0;   // counts accepted with a weak pivot after the nudges ran out
 };
 
-// nu at sigma; a shift that hits an exact zero pivot moves by `nudge` (repeatedly).
+// A count is trusted when no pivot is zero, the smallest pivot is not below
+// kWeakPivotRel * ||A - sigma B||_inf and no multiplier exceeds kGrowthMax: the
+// count is exact for A - sigma B + E with E of the size of the factorization's
+// backward error, so a shift within that distance of an eigenvalue, or a
+// factorization with large element growth (pivoting is restricted to the
+// fully-summed block), could count an eigenvalue on the wrong side.
+constexpr double kWeakPivotRel = 1e-13;
+constexpr double kGrowthMax = 1e8;
+bool weak_count(int64_t zero, double md, double maxl, double scale) {
+  return zero != 0 || md < kWeakPivotRel * scale || !(maxl <= kGrowthMax);
+}
+
+// nu at sigma; a shift with a zero or weak pivot, or with large growth, moves by
+// `nudge` (growing with the attempt) and is counted again.  Zero pivots that
+// persist are an error; a weak but nonzero pivot that persists is accepted (and
+// reported) after kWeakAttempts moves.
+constexpr int kWeakAttempts = 3;
 int64_t nu_checked(Pencil& P, double& sigma, double nudge, Shifts& log, int64_t* nfac) {
   for (int attempt = 0; attempt < 8; attempt++) {
     int64_t zero = 0;
-    double md = 0;
-    int64_t nu = count_nu(P, sigma, &zero, &md);
+    double md = 0, ml = 0;
+    int64_t nu = count_nu(P, sigma, &zero, &md, &ml);
     (*nfac)++;
     double scale = P.normA_inf + std::fabs(sigma) * P.normB_inf;
-    if (scale > 0) log.min_pivot_rel = std::min(log.min_pivot_rel, md / scale);
-    if (zero == 0) {
+    bool weak = weak_count(zero, md, ml, scale);
+    if (zero == 0 && (!weak || attempt >= kWeakAttempts)) {
+      if (scale > 0) log.min_pivot_rel = std::min(log.min_pivot_rel, md / scale);
+      log.max_abs_l = std::max(log.max_abs_l, ml);
+      if (weak) log.weak_kept++;
       log.s.push_back(sigma);
       log.nu.push_back(nu);
       return nu;
     }
+    log.nudges++;
     sigma += nudge * (attempt + 1);
   }
   throw Error(KTH_ESINGULAR, "repeated zero pivots near sigma");
@@ -330,8 +356,10 @@ void solve_many(Pencil& P, NumFactor& F, int32_t nrhs, const double* r, int64_t 
 
 // nu at many shifts: batches of factorizations advancing together through the
 // level schedule (one launch sequence per batch); returns the zero-pivot count.
+// weak (may be null): per shift, whether the count fails the trust test of
+// nu_checked (zero or weak pivot, or large growth).
 int64_t inertia_batch_counts(Pencil& P, int32_t nsigma, const double* sigmas, int64_t* nu,
-                             int64_t* nzero) {
+                             int64_t* nzero, uint8_t* weak = nullptr) {
   if (nsigma <= 0) return 0;
   const int cap = factor_batch_capacity(P, nsigma);
   if (!P.batchF || P.batchF->nb < cap) {
@@ -345,9 +373,15 @@ int64_t inertia_batch_counts(Pencil& P, int32_t nsigma, const double* sigmas, in
     factor_enqueue_batch(P, F, sigmas + i, nb, false);
     factor_read_stats(P, F, nb);
     for (int q = 0; q < nb; q++) {
-      nu[i + q] = (int64_t)F.hsb[q].neg;
-      if (nzero) nzero[i + q] = (int64_t)F.hsb[q].zero;
-      zeros += (int64_t)F.hsb[q].zero;
+      const FactStats& h = F.hsb[q];
+      nu[i + q] = (int64_t)h.neg;
+      if (nzero) nzero[i + q] = (int64_t)h.zero;
+      if (weak) {
+        const double scale = P.normA_inf + std::fabs(sigmas[i + q]) * P.normB_inf;
+        weak[i + q] = weak_count((int64_t)h.zero, bits_to_double(h.min_d_bits),
+                                 bits_to_double(h.max_l_bits), scale);
+      }
+      zeros += (int64_t)h.zero;
     }
   }
   return zeros;
@@ -389,7 +423,7 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
 
   double sl, su;
   int64_t nl, nu_;
-  int s1 = 0, s2 = 0;
+  int s1 = 0, s2 = 0, s1_restarts = 0;
   if (o.warm_interval && o.warm_counts) {
     sl = o.warm_interval[0];
     su = o.warm_interval[1];
@@ -448,6 +482,7 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
         double beta = std::sqrt(std::max(dot_dev(W, W.w.get(), W.Bw.get()), 0.0));
         if (!(beta > 1e-14 * std::max(1.0, std::fabs(al.back())))) {
           if (++restart > 2) throw Error(KTH_ENOCONV, "stage-1 Lanczos broke down repeatedly");
+          s1_restarts = restart;
           break;   // restart with the next seeded vector
         }
         be.push_back(beta);
@@ -468,11 +503,12 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
       } else {
         std::vector<double> sg(ms);
         std::vector<int64_t> cnt(ms), zc(ms);
+        std::vector<uint8_t> wk(ms);
         for (int i = 0; i < ms; i++) sg[i] = sl + (su - sl) * (double)(i + 1) / (double)(ms + 1);
-        inertia_batch_counts(P, ms, sg.data(), cnt.data(), zc.data());
+        inertia_batch_counts(P, ms, sg.data(), cnt.data(), zc.data(), wk.data());
         nfac += ms;
         for (int i = 0; i < ms; i++) {
-          if (zc[i] != 0) {   // move that shift and count again on its own
+          if (wk[i]) {   // move that shift and count again on its own
             nfac--;
             cnt[i] = nu_checked(P, sg[i], 1e-3 * (su - sl) / (ms + 1), log, &nfac);
           } else {
@@ -511,8 +547,22 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
       factor_enqueue(P, FS, sigma, false);
       factor_read_stats(P, FS);
       nfac++;
-      if (FS.hs.zero == 0) break;
+      const double md = bits_to_double(FS.hs.min_d_bits), ml = bits_to_double(FS.hs.max_l_bits);
+      const double scale = P.normA_inf + std::fabs(sigma) * P.normB_inf;
+      // the FP64 factor's count is checked against the interval below, so a weak
+      // pivot or large growth there moves the shift too (FP32: zero pivots only)
+      const bool weak = prec == KTH_FP64 ? weak_count((int64_t)FS.hs.zero, md, ml, scale)
+                                         : FS.hs.zero != 0;
+      if (FS.hs.zero == 0 && (!weak || attempt >= kWeakAttempts)) {
+        if (prec == KTH_FP64) {
+          if (scale > 0) log.min_pivot_rel = std::min(log.min_pivot_rel, md / scale);
+          log.max_abs_l = std::max(log.max_abs_l, ml);
+          if (weak) log.weak_kept++;
+        }
+        break;
+      }
       if (attempt > 6) throw Error(KTH_ESINGULAR, "shift-and-invert factor keeps hitting zero pivots");
+      log.nudges++;
       sigma += 1e-3 * (su - sl);
     }
     // the FP64 count is exact; the FP32 one only serves the factor itself
@@ -690,6 +740,10 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   info->it_difference = it_diff;
   info->eta = eta_out;
   info->min_pivot_rel = log.min_pivot_rel;
+  info->max_abs_l = log.max_abs_l;
+  info->weak_pivot_nudges = log.nudges;
+  info->weak_pivot_kept = log.weak_kept;
+  info->stage1_restarts = s1_restarts;
   info->n_factorizations = nfac;
   info->flops_factor = P.S.flops;
   for (int q = 0; q < 7; q++) info->t_task[q] = t_task[q];

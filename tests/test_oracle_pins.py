@@ -166,3 +166,43 @@ def test_hf_gradient_matches_finite_differences():
             g = gA if which == "a" else gB
             an = g[q] + (g[q2] if q2 != q else 0.0)
             assert abs(fd - an) <= 1e-7 + 1e-5 * abs(an), (which, i, j, fd, an)
+
+
+def test_norm_inf_hand_computed():
+    # rows of A: |1| + |-2| + |0| = 3, |-2| + |3| + |4| = 9, |0| + |4| + |-6| = 10
+    rowptr = np.array([0, 3, 6, 9], dtype=np.int64)
+    col = np.array([0, 1, 2] * 3, dtype=np.int32)
+    a = np.array([1.0, -2.0, 0.0, -2.0, 3.0, 4.0, 0.0, 4.0, -6.0])
+    p = pg.Pencil(n=3, rowptr=rowptr, col=col, a_val=a, b_val=np.eye(3).ravel())
+    assert od.norm_inf(p) == 10.0
+    # a pattern with rows of different lengths (and an empty off-diagonal part)
+    q = pg.chain(5, 0.5, -1.25)        # rows: 1.75, 3.0, 3.0, 3.0, 1.75
+    assert od.norm_inf(q) == 3.0
+
+
+def test_dense_eigvals_closed_form():
+    N, w = (5, 4, 6), (1.0, 2.1, 0.6)
+    ref = fem_eigs(N, w)
+    lam = od.eigvals(pg.fem_tensor(N, w))
+    assert np.allclose(lam, ref, rtol=1e-12, atol=1e-9 * ref.max())
+    p = pg.block_diag_perm((6, 3, 8), seed=11)
+    blk = np.sort(np.concatenate([sla.eigh(a, b, eigvals_only=True) for a, b in p.blocks]))
+    assert np.allclose(od.eigvals(p), blk, atol=1e-12)
+
+
+def test_stored_oracle_isolation_tiny():
+    """The oracle-only isolation job (multisection -> shift-and-invert Lanczos ->
+    inertia certificate) on the small workload, against the dense definition."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "kth_oracle_tiny.json")
+    g = json.load(open(path))
+    p = pg.workload("tiny")
+    lam = od.eigvals(p)
+    assert g["k"] == p.k and g["phase"] == "done" and g["certificate"]["holds"]
+    assert abs(g["lam"] - lam[p.k - 1]) <= 1e-12 * od.norm_inf(p)
+    for s, nu, zero in g["counts"]:
+        assert zero == 0 and nu == od.nu(lam, s)
+    c = g["certificate"]
+    assert c["sigma_minus"] <= lam[p.k - 1] < c["sigma_plus"]
