@@ -20,11 +20,13 @@
  * Everything here is independent of the GPU library: its own ordering input,
  * its own symbolic analysis, its own numeric kernels.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 typedef struct {
   int64_t neg, zero, pos;
@@ -110,15 +112,105 @@ static void count_2x2(double a, double b, double c, orc_stats *st) {
 }
 
 /*
+ * Partial factorization of the ns fully-summed columns of the nf x nf front F
+ * (column-major, lower triangle used), Bunch-Kaufman pivoting with candidates
+ * among the fully-summed rows (Section 2.1; alpha = (1 + sqrt 17) / 8); at most
+ * cap pivot columns when cap > 0.  lp: pivot order within the block (ns entries,
+ * initialised to the identity by the caller).  D, E (may be NULL): pivots and
+ * 2x2 off-diagonals of the block.  Returns the number of columns eliminated.
+ */
+static int64_t partial_factor(double *F, int64_t nf, int64_t ns, int64_t cap, int64_t *lp,
+                              orc_stats *st, double *D, double *E) {
+  const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+#define FA(i, j) F[(i) + (j) * nf]
+  int64_t k = 0;
+  while (k < ns && (cap <= 0 || k < cap)) {
+    double g1 = 0; int64_t r = k;
+    for (int64_t i = k + 1; i < ns; i++) if (fabs(FA(i, k)) > g1) { g1 = fabs(FA(i, k)); r = i; }
+    int two = 0;
+    if (g1 == 0 || fabs(FA(k, k)) >= alpha * g1) {
+      /* 1x1 at k */
+    } else {
+      double gr = 0;
+      for (int64_t i = k; i < ns; i++) if (i != r) {
+        double v = i < r ? fabs(FA(r, i)) : fabs(FA(i, r));
+        if (v > gr) gr = v;
+      }
+      if (fabs(FA(k, k)) * gr >= alpha * g1 * g1) {
+        /* 1x1 at k */
+      } else if (fabs(FA(r, r)) >= alpha * gr) {
+        sym_swap(F, nf, k, r);
+        int64_t t = lp[k]; lp[k] = lp[r]; lp[r] = t;
+      } else {
+        two = 1;
+        if (r != k + 1) {
+          sym_swap(F, nf, k + 1, r);
+          int64_t t = lp[k + 1]; lp[k + 1] = lp[r]; lp[r] = t;
+        }
+      }
+    }
+    if (!two) {
+      double d = FA(k, k);
+      count_1x1(d, st);
+      if (D) { D[k] = d; E[k] = 0; }
+      if (d != 0) {
+        /* trailing -= F(:,k) F(:,k)^T / d  (lower triangle) */
+        for (int64_t j = k + 1; j < nf; j++) {
+          double wj = FA(j, k);
+          if (wj == 0) continue;
+          for (int64_t i = j; i < nf; i++) FA(i, j) -= FA(i, k) * (wj / d);
+        }
+        for (int64_t i = k + 1; i < nf; i++) {
+          FA(i, k) /= d;
+          if (fabs(FA(i, k)) > st->max_abs_l) st->max_abs_l = fabs(FA(i, k));
+        }
+      } else {
+        for (int64_t i = k + 1; i < nf; i++) FA(i, k) = 0;   /* zero pivot: recorded, skipped */
+      }
+      FA(k, k) = 1.0;
+      k += 1;
+    } else {
+      double a = FA(k, k), b = FA(k + 1, k), c = FA(k + 1, k + 1);
+      double det = a * c - b * b;
+      count_2x2(a, b, c, st);
+      st->n2x2++;
+      if (D) { D[k] = a; E[k] = b; D[k + 1] = c; E[k + 1] = 0; }
+      /* W = [F(:,k) F(:,k+1)], L = W D^{-1}, trailing -= L W^T */
+      for (int64_t j = k + 2; j < nf; j++) {
+        double w1 = FA(j, k), w2 = FA(j, k + 1);
+        for (int64_t i = j; i < nf; i++) {
+          double l1 = (c * FA(i, k) - b * FA(i, k + 1)) / det;
+          double l2 = (a * FA(i, k + 1) - b * FA(i, k)) / det;
+          FA(i, j) -= l1 * w1 + l2 * w2;
+        }
+      }
+      for (int64_t i = k + 2; i < nf; i++) {
+        double w1 = FA(i, k), w2 = FA(i, k + 1);
+        FA(i, k) = (c * w1 - b * w2) / det;
+        FA(i, k + 1) = (a * w2 - b * w1) / det;
+        if (fabs(FA(i, k)) > st->max_abs_l) st->max_abs_l = fabs(FA(i, k));
+        if (fabs(FA(i, k + 1)) > st->max_abs_l) st->max_abs_l = fabs(FA(i, k + 1));
+      }
+      FA(k, k) = 1.0; FA(k + 1, k) = 0.0; FA(k + 1, k + 1) = 1.0;
+      k += 2;
+    }
+  }
+#undef FA
+  return k;
+}
+
+/*
  * orc_ldlt: factor Q C Q^T, C = A - sigma B given as symmetric CSR (both
  * triangles, sorted columns).  perm[k] = original index eliminated k-th before
  * postordering (NULL: identity).  keep != 0 keeps L, D for orc_solve.
  * flop_cap > 0 stops after the supernode whose cumulative count passes it
- * (stats.completed = 0 then).  Returns 0, or -1 on invalid input.
+ * (stats.completed = 0 then).  shapes (may be NULL; room for 2 n entries)
+ * receives (nf, ns) of every supernode in elimination order (stats.nsuper of them).
+ * Returns 0, or -1 on invalid input.
  */
 int orc_ldlt(int64_t n, const int64_t *rowptr, const int32_t *col, const double *aval,
              const double *bval, double sigma, const int64_t *perm_in, int keep,
-             double flop_cap, orc_stats *st, orc_factor **out) {
+             double flop_cap, orc_stats *st, orc_factor **out, int64_t *shapes) {
   memset(st, 0, sizeof(*st));
   st->min_abs_d = INFINITY;
   st->completed = 1;
@@ -243,6 +335,11 @@ int orc_ldlt(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
   st->nnz_l = (int64_t)nnzl;
   st->flops = flops;
   st->nsuper = nsup;
+  if (shapes)
+    for (int64_t s = 0; s < nsup; s++) {
+      shapes[2 * s] = rptr[s + 1] - rptr[s];
+      shapes[2 * s + 1] = sfirst[s + 1] - sfirst[s];
+    }
 
   /* supernode of each column, supernode parents and child lists */
   int64_t *snode = xmalloc(sizeof(int64_t) * n);
@@ -278,7 +375,6 @@ int orc_ldlt(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
   }
 
   /* ---- numeric multifrontal factorization ---- */
-  const double alpha = (1.0 + sqrt(17.0)) / 8.0;
   double **U = xcalloc(nsup, sizeof(double *));   /* update matrices awaiting parents */
   double done = 0;
   int64_t maxf = 0;
@@ -314,78 +410,7 @@ int orc_ldlt(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
        with candidates among the fully-summed rows */
     int64_t *lp = xmalloc(sizeof(int64_t) * (ns ? ns : 1));
     for (int64_t k = 0; k < ns; k++) lp[k] = k;
-    int64_t k = 0;
-    while (k < ns) {
-      double g1 = 0; int64_t r = k;
-      for (int64_t i = k + 1; i < ns; i++) if (fabs(FA(i, k)) > g1) { g1 = fabs(FA(i, k)); r = i; }
-      int two = 0;
-      if (g1 == 0 || fabs(FA(k, k)) >= alpha * g1) {
-        /* 1x1 at k */
-      } else {
-        double gr = 0;
-        for (int64_t i = k; i < ns; i++) if (i != r) {
-          double v = i < r ? fabs(FA(r, i)) : fabs(FA(i, r));
-          if (v > gr) gr = v;
-        }
-        if (fabs(FA(k, k)) * gr >= alpha * g1 * g1) {
-          /* 1x1 at k */
-        } else if (fabs(FA(r, r)) >= alpha * gr) {
-          sym_swap(F, nf, k, r);
-          int64_t t = lp[k]; lp[k] = lp[r]; lp[r] = t;
-        } else {
-          two = 1;
-          if (r != k + 1) {
-            sym_swap(F, nf, k + 1, r);
-            int64_t t = lp[k + 1]; lp[k + 1] = lp[r]; lp[r] = t;
-          }
-        }
-      }
-      if (!two) {
-        double d = FA(k, k);
-        count_1x1(d, st);
-        if (fac) { fac->D[f + k] = d; fac->E[f + k] = 0; }
-        if (d != 0) {
-          /* trailing -= F(:,k) F(:,k)^T / d  (lower triangle) */
-          for (int64_t j = k + 1; j < nf; j++) {
-            double wj = FA(j, k);
-            if (wj == 0) continue;
-            for (int64_t i = j; i < nf; i++) FA(i, j) -= FA(i, k) * (wj / d);
-          }
-          for (int64_t i = k + 1; i < nf; i++) {
-            FA(i, k) /= d;
-            if (fabs(FA(i, k)) > st->max_abs_l) st->max_abs_l = fabs(FA(i, k));
-          }
-        } else {
-          for (int64_t i = k + 1; i < nf; i++) FA(i, k) = 0;   /* zero pivot: recorded, skipped */
-        }
-        FA(k, k) = 1.0;
-        k += 1;
-      } else {
-        double a = FA(k, k), b = FA(k + 1, k), c = FA(k + 1, k + 1);
-        double det = a * c - b * b;
-        count_2x2(a, b, c, st);
-        st->n2x2++;
-        if (fac) { fac->D[f + k] = a; fac->E[f + k] = b; fac->D[f + k + 1] = c; fac->E[f + k + 1] = 0; }
-        /* W = [F(:,k) F(:,k+1)], L = W D^{-1}, trailing -= L W^T */
-        for (int64_t j = k + 2; j < nf; j++) {
-          double w1 = FA(j, k), w2 = FA(j, k + 1);
-          for (int64_t i = j; i < nf; i++) {
-            double l1 = (c * FA(i, k) - b * FA(i, k + 1)) / det;
-            double l2 = (a * FA(i, k + 1) - b * FA(i, k)) / det;
-            FA(i, j) -= l1 * w1 + l2 * w2;
-          }
-        }
-        for (int64_t i = k + 2; i < nf; i++) {
-          double w1 = FA(i, k), w2 = FA(i, k + 1);
-          FA(i, k) = (c * w1 - b * w2) / det;
-          FA(i, k + 1) = (a * w2 - b * w1) / det;
-          if (fabs(FA(i, k)) > st->max_abs_l) st->max_abs_l = fabs(FA(i, k));
-          if (fabs(FA(i, k + 1)) > st->max_abs_l) st->max_abs_l = fabs(FA(i, k + 1));
-        }
-        FA(k, k) = 1.0; FA(k + 1, k) = 0.0; FA(k + 1, k + 1) = 1.0;
-        k += 2;
-      }
-    }
+    partial_factor(F, nf, ns, 0, lp, st, fac ? fac->D + f : NULL, fac ? fac->E + f : NULL);
     /* keep L panel, hand the update matrix to the parent */
     if (fac) {
       memcpy(fac->L + fac->lptr[s], F, sizeof(double) * nf * ns);
@@ -419,6 +444,44 @@ int orc_ldlt(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
     if (fac) { free(fac->lptr); free(fac->L); free(fac->D); free(fac->E); free(fac->lperm); free(fac); }
     free(perm); free(sfirst); free(rptr); free(rows);
   }
+  return 0;
+}
+
+/*
+ * Timing sample (CPU baseline, not part of the oracle's results): the partial
+ * factorization above on one synthetic dense front of nf rows with ns
+ * fully-summed columns, at most cap pivots (cap <= 0: all ns).  Entries of the
+ * lower triangle are uniform in [-1, 1) from a fixed 64-bit linear congruential
+ * sequence.  secs: wall time of the factorization alone; flops: its algorithmic
+ * count, sum over the pivot columns taken of c^2 + 2c (c = rows below the pivot).
+ */
+int orc_front_sample(int64_t nf, int64_t ns, int64_t cap, double *secs, double *flops) {
+  if (nf <= 0 || ns <= 0 || ns > nf) return -1;
+  double *F = xmalloc(sizeof(double) * nf * nf);
+  uint64_t x = 0x2545F4914F6CDD1Dull;
+  for (int64_t j = 0; j < nf; j++)
+    for (int64_t i = j; i < nf; i++) {
+      x = x * 6364136223846793005ull + 1442695040888963407ull;
+      F[i + j * nf] = (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+  int64_t *lp = xmalloc(sizeof(int64_t) * ns);
+  for (int64_t k = 0; k < ns; k++) lp[k] = k;
+  orc_stats st;
+  memset(&st, 0, sizeof(st));
+  st.min_abs_d = INFINITY;
+  struct timespec t0, t1;
+  clock_gettime(CLOCK_MONOTONIC, &t0);
+  int64_t done = partial_factor(F, nf, ns, cap, lp, &st, NULL, NULL);
+  clock_gettime(CLOCK_MONOTONIC, &t1);
+  *secs = (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
+  double fl = 0;
+  for (int64_t jj = 0; jj < done; jj++) {
+    double c = (double)(nf - 1 - jj);
+    fl += c * c + 2 * c;
+  }
+  *flops = fl;
+  free(lp);
+  free(F);
   return 0;
 }
 

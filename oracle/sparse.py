@@ -36,7 +36,9 @@ def lib():
         L = C.CDLL(_build.LIB)
         p64, pi32, pd = C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)
         L.orc_ldlt.argtypes = [C.c_int64, p64, pi32, pd, pd, C.c_double, p64, C.c_int,
-                               C.c_double, C.POINTER(Stats), C.POINTER(C.c_void_p)]
+                               C.c_double, C.POINTER(Stats), C.POINTER(C.c_void_p), p64]
+        L.orc_front_sample.argtypes = [C.c_int64, C.c_int64, C.c_int64, pd, pd]
+        L.orc_front_sample.restype = C.c_int
         L.orc_ldlt.restype = C.c_int
         L.orc_solve.argtypes = [C.c_void_p, pd, pd]
         L.orc_solve.restype = C.c_int
@@ -76,10 +78,34 @@ def ldlt_stats(pencil, sigma: float, flop_cap: float = 0.0) -> Stats:
     st = Stats()
     rc = lib().orc_ldlt(P.n, _ptr(P.rowptr, C.c_int64), _ptr(P.col, C.c_int32),
                         _ptr(P.a, C.c_double), _ptr(P.b, C.c_double), float(sigma),
-                        _ptr(P.perm, C.c_int64), 0, float(flop_cap), C.byref(st), None)
+                        _ptr(P.perm, C.c_int64), 0, float(flop_cap), C.byref(st), None, None)
     if rc != 0:
         raise ValueError("oracle LDL^T rejected its input")
     return st
+
+
+def front_shapes(pencil):
+    """(nf, ns) of every supernode of the oracle's own symbolic analysis, in
+    elimination order (int64 array of shape (nsuper, 2)), and the flop total."""
+    P = prepare(pencil)
+    st = Stats()
+    shapes = np.zeros(2 * P.n, dtype=np.int64)
+    rc = lib().orc_ldlt(P.n, _ptr(P.rowptr, C.c_int64), _ptr(P.col, C.c_int32),
+                        _ptr(P.a, C.c_double), _ptr(P.b, C.c_double), 0.0,
+                        _ptr(P.perm, C.c_int64), 0, 1.0, C.byref(st), None,
+                        _ptr(shapes, C.c_int64))
+    if rc != 0:
+        raise ValueError("oracle LDL^T rejected its input")
+    return shapes[: 2 * st.nsuper].reshape(-1, 2), float(st.flops)
+
+
+def front_sample(nf: int, ns: int, cap: int = 0) -> tuple[float, float]:
+    """(seconds, flops) of the oracle's partial factorization of one synthetic
+    dense front (timing sample for the CPU baseline; see orc_front_sample)."""
+    secs, fl = C.c_double(), C.c_double()
+    if lib().orc_front_sample(int(nf), int(ns), int(cap), C.byref(secs), C.byref(fl)) != 0:
+        raise ValueError("bad front shape")
+    return secs.value, fl.value
 
 
 def inertia(pencil, sigma: float) -> tuple[int, int, int]:
@@ -106,7 +132,7 @@ class Factor:
         P = self.P
         rc = lib().orc_ldlt(P.n, _ptr(P.rowptr, C.c_int64), _ptr(P.col, C.c_int32),
                             _ptr(P.a, C.c_double), _ptr(P.b, C.c_double), self.sigma,
-                            _ptr(P.perm, C.c_int64), 1, 0.0, C.byref(self.stats), C.byref(h))
+                            _ptr(P.perm, C.c_int64), 1, 0.0, C.byref(self.stats), C.byref(h), None)
         if rc != 0 or not h.value:
             raise ValueError("oracle LDL^T failed")
         self._h = h
