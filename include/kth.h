@@ -127,6 +127,27 @@ kth_status kth_factor_inertia(kth_factor_t f, int64_t* neg, int64_t* zero, int64
 kth_status kth_solve(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr, double* x,
                      int64_t ldx, uint32_t flags);
 kth_status kth_factor_destroy(kth_factor_t f);
+
+/* Allocation-free solve, for callers that cannot allocate device memory (work
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same X = (A - sigma B)^{-1} R as kth_solve with KTH_DEVICE_PTRS, bit for bit,
+ * for an FP64 factor, or one unrefined pass of an FP32 factor (flags must then hold
+ * KTH_SOLVE_UNREFINED: refinement allocates).  r, x: DEVICE pointers, column-major,
+ * leading dimensions >= n.  The solve's work vectors come from one fixed array of
+ * KTH_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on (its
+ * address is taken when a context is created on that GPU); a factor whose solve
+ * needs more -- 8 (2 n + total front rows + backward partial sums) bytes; the
+ * factors of the n = 524288 tight-binding workload fit -- is rejected with
+ * KTH_EINVAL before anything is enqueued.
+ * The call only enqueues kernels on the context's stream and returns (no
+ * synchronisation): synchronise that stream before reading x.  It calls no
+ * hipMalloc or hipFree.  All calls on one GPU share that GPU's array: calls that
+ * overlap in time on one GPU (other streams, contexts or threads) race, calls on
+ * one stream run in order.  Every part of the array a call reads is first written
+ * by that call, so what an earlier call left there does not matter. */
+#define KTH_NOALLOC_SCRATCH_BYTES (64u << 20)
+kth_status kth_solve_noalloc(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr, double* x,
+                             int64_t ldx, uint32_t flags);
 /* Pivot statistics of a kept factor (FP64 or FP32): n2x2 = number of 2x2 blocks of
  * D; min_pivot_rel = smallest |eigenvalue of a D block| / (||A||_inf + |sigma|
  * ||B||_inf); max_abs_l = largest |L_ij| (element growth of the restricted

@@ -98,6 +98,7 @@ def lib() -> C.CDLL:
         "kth_solve": ([vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, C.c_uint32], C.c_int),
         "kth_factor_destroy": ([vp], C.c_int),
         "kth_factor_stats": ([vp, p64, pd, pd], C.c_int),
+        "kth_solve_noalloc": ([vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, C.c_uint32], C.c_int),
         "kth_opts_default": ([C.POINTER(kth_opts)], None),
         "kth_eig": ([vp, C.c_int64, C.POINTER(kth_opts), pd, pd, C.POINTER(kth_info)], C.c_int),
         "kth_eig_batch": ([vp, C.c_int32, C.POINTER(vp), p64, C.POINTER(kth_opts), pd,

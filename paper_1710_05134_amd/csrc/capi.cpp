@@ -14,6 +14,9 @@
 
 using namespace kth;
 
+static_assert(KTH_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes,
+              "the header's work-array size must match the library's");
+
 // Handles are reference counted: a pencil holds its context, a factor its pencil,
 // so the device memory of a child is released through a live parent whatever the
 // order in which the caller destroys them.
@@ -128,6 +131,8 @@ kth_status kth_ctx_create(int device, void* hip_stream, kth_alloc_fn alloc, kth_
       throw Error(KTH_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
     c->c.device = device;
     KTH_HIP(hipSetDevice(device));
+    // address of this device's work array for kth_solve_noalloc (once per device)
+    KTH_HIP(noalloc_scratch_init(device));
     if (hip_stream) {
       c->c.stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -300,6 +305,19 @@ kth_status kth_solve(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr,
     set_device(p->ctx->c);
     solve_many(p->p, f->f, nrhs, r, ldr, x, ldx, (flags & KTH_DEVICE_PTRS) != 0,
                (flags & KTH_SOLVE_UNREFINED) != 0);
+  });
+}
+
+kth_status kth_solve_noalloc(kth_factor_t f, int32_t nrhs, const double* r, int64_t ldr, double* x,
+                             int64_t ldx, uint32_t flags) {
+  if (!f || !r || !x || nrhs < 0) return KTH_EINVAL;
+  kth_pencil_s* p = f->pen;
+  return guarded(&p->ctx->c, [&] {
+    if (ldr < p->p.n || ldx < p->p.n) throw Error(KTH_EINVAL, "leading dimension smaller than n");
+    if (f->f.prec != KTH_FP64 && !(flags & KTH_SOLVE_UNREFINED))
+      throw Error(KTH_EINVAL, "an FP32 factor needs KTH_SOLVE_UNREFINED here (refinement allocates)");
+    set_device(p->ctx->c);
+    solve_noalloc(p->p, f->f, nrhs, r, ldr, x, ldx);
   });
 }
 

@@ -714,4 +714,30 @@ void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x) {
                          F.ye.get(), F.R.get(), F.partial.get(), c->stream);
 }
 
+void solve_noalloc(Pencil& P, NumFactor& F, int32_t nrhs, const double* r, int64_t ldr, double* x,
+                   int64_t ldx) {
+  double* base = noalloc_scratch(P.ctx->device);
+  if (!base) throw Error(KTH_ESTATE, "no work array address for this device");
+  auto up = [](size_t v) { return (v + 31) / 32 * 32; };   // 256-byte pieces
+  const size_t n = (size_t)P.n;
+  const size_t o_ye = up(n), o_r = o_ye + up(n), o_p = o_r + up(P.S.rows.size());
+  const size_t need = o_p + up((size_t)P.splan.partial_size);
+  if (need * sizeof(double) > kNoAllocScratchBytes)
+    throw Error(KTH_EINVAL, "this factor's solve needs " + std::to_string(need * sizeof(double)) +
+                                " bytes of work array; the allocation-free solve has " +
+                                std::to_string(kNoAllocScratchBytes));
+  for (int32_t q = 0; q < nrhs; q++) {
+    const double* b = r + (size_t)q * ldr;
+    double* xq = x + (size_t)q * ldx;
+    if (F.prec == KTH_FP64)
+      solve_enqueue<double>(P.splan, P.meta, F.L.get(), F.D.get(), F.E.get(), F.tperm.get(),
+                            P.d_perm.get(), P.n, b, xq, base, base + o_ye, base + o_r, base + o_p,
+                            P.ctx->stream);
+    else
+      solve_enqueue<float>(P.splan, P.meta, reinterpret_cast<const float*>(F.L.get()), F.D.get(),
+                           F.E.get(), F.tperm.get(), P.d_perm.get(), P.n, b, xq, base, base + o_ye,
+                           base + o_r, base + o_p, P.ctx->stream);
+  }
+}
+
 }  // namespace kth

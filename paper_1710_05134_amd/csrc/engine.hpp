@@ -205,5 +205,10 @@ void factor_read_stats(Pencil& P, NumFactor& F);
 void factor_read_stats(Pencil& P, NumFactor& F, int nb);
 // x = (A - sigma B)^{-1} b, device vectors (enqueue only).
 void solve_enqueue_f(Pencil& P, NumFactor& F, const double* b, double* x);
+// The same for nrhs device columns with the work vectors in the per-GPU fixed array
+// (noalloc_scratch): no device allocation; enqueue only.  Throws KTH_EINVAL when
+// the factor's solve needs more than kNoAllocScratchBytes.
+void solve_noalloc(Pencil& P, NumFactor& F, int32_t nrhs, const double* r, int64_t ldr, double* x,
+                   int64_t ldx);
 
 }  // namespace kth

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <vector>
 
 #include "device.hpp"
 #include "solve.hpp"
@@ -445,6 +447,35 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
                          sc + lv.large_off, L, tperm, ye, P.pbase, partial, xe);
   }
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, s, n, perm, xe, x);
+}
+
+// ---- work array of the allocation-free solve (kth_solve_noalloc) -----------
+// A __device__ object has one instance on every GPU the code object is loaded on.
+// Its name is only a host-side stand-in: host code uses the per-device address
+// that hipGetSymbolAddress returns (taken once per device, with that device
+// current, when a context is created) and passes it to the kernels.
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // indexed by device
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return device >= 0 && device < (int)g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
 }
 
 template void solve_enqueue<double>(const SolvePlan&, const FrontMeta&, const double*, const double*,

@@ -31,6 +31,14 @@ struct SolvePlan {
   const int64_t* pbase = nullptr;    // device [nsup]: a large front's first slot in its level
 };
 
+// Size of the fixed per-GPU work array of the allocation-free solve.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+// Takes the address of that array on `device` (which must be current) once per
+// device; returns the HIP error of hipGetSymbolAddress (hipSuccess when known).
+hipError_t noalloc_scratch_init(int device);
+// The array's device address on `device` (nullptr before noalloc_scratch_init).
+double* noalloc_scratch(int device);
+
 // x = (A - sigma B)^{-1} b with a kept factor (T = double or float panels).
 // xe, ye: n-vectors of scratch; R: work vectors (rows.size() doubles);
 // partial: P.partial_size doubles.
