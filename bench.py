@@ -12,13 +12,17 @@ Printed: one JSON line with the step time (`value`, seconds, lower is better),
 the LDL^T GFLOP/s of one factorization at the first bisection shift, the
 roofline of the dominant kernel (k_gemm_lt, the FP64-MFMA left-looking and
 contribution-block products) from HIP events around its launches, and the CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  Extra legs (each
+skippable with --skip): `hbm` (event-timed solve and SpMV bandwidth at the
+shift-and-invert shift), `fp32_ir` (the same run with the FP32 shift-and-invert
+factor and FP64 refinement), `c3a` (64 shifts of the n = 131072 pencil per
+round against one at a time and against bisection), `c3b` (256 uneven pencils
+in one batched call against a loop of single calls).
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import statistics
 import sys
@@ -36,30 +40,86 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pencil, sigma: float, n_factorizations: int, sample_flops: float):
-    """The oracle's sparse LDL^T on the same pencil, stopped after `sample_flops`
-    (its first fronts in postorder); projected to the run's factorization count."""
+def _cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+# front-size classes (rows of the front) for the CPU baseline's sample
+CPU_CLASSES = (0, 128, 512, 2048, 8192, 1 << 40)
+
+
+def _front_flops(nf, ns):
+    """sum over the ns pivot columns of c^2 + 2c, c = nf - 1 - j (vectorised)."""
+    import numpy as np
+    hi = nf.astype(np.float64) - 1.0          # c of the first pivot
+    lo = hi - ns.astype(np.float64) + 1.0     # c of the last
+    s1 = lambda m: m * (m + 1.0) / 2.0
+    s2 = lambda m: m * (m + 1.0) * (2.0 * m + 1.0) / 6.0
+    return (s2(hi) - s2(lo - 1.0)) + 2.0 * (s1(hi) - s1(lo - 1.0))
+
+
+def cpu_baseline(pencil, n_factorizations: int, per_class=4, sample_flops=1.5e9):
+    """The oracle's sparse LDL^T, projected from a bounded sample: its own ordering
+    and symbolic analysis are timed whole; its partial factorization of a front
+    (the flop sink) is timed on synthetic fronts of the workload's own shapes, a
+    few per front-size class (the largest fronts capped at `sample_flops` of their
+    first pivots), and each class's rate weights that class's share of the flops."""
+    import numpy as np
     from oracle import sparse as osp
     t0 = time.perf_counter()
     P = osp.prepare(pencil)
     t_order = time.perf_counter() - t0
     t0 = time.perf_counter()
-    osp.ldlt_stats(P, sigma, flop_cap=1.0)          # symbolic analysis only (+ one front)
+    shapes, F = osp.front_shapes(P)
     t_sym = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    st = osp.ldlt_stats(P, sigma, flop_cap=sample_flops)
-    t_all = time.perf_counter() - t0
-    t_num = max(t_all - t_sym, 1e-9)
-    rate = st.flops_done / t_num
-    per_fact = t_sym + st.flops / rate
+    nf, ns = shapes[:, 0], shapes[:, 1]
+    fl = _front_flops(nf, ns)
+    per_fact = t_sym
+    parts, t_sample = [], 0.0
+    for lo, hi in zip(CPU_CLASSES[:-1], CPU_CLASSES[1:]):
+        idx = np.nonzero((nf >= lo) & (nf < hi))[0]
+        if idx.size == 0:
+            continue
+        fc = float(fl[idx].sum())
+        order = idx[np.argsort(fl[idx], kind="stable")]
+        picks = order[np.unique(np.linspace(0, order.size - 1, per_class).round().astype(int))]
+        secs = flops = 0.0
+        for q in picks:
+            a, b = int(nf[q]), int(ns[q])
+            # pivot cap: the first pivots of the front within sample_flops
+            c = np.arange(a - 1, a - 1 - b, -1, dtype=np.float64)
+            cum = np.cumsum(c * c + 2 * c)
+            cap = int(np.searchsorted(cum, sample_flops)) + 1
+            cap = 0 if cap >= b else cap
+            s_, f_ = osp.front_sample(a, b, cap)
+            secs += s_
+            flops += f_
+        rate = flops / max(secs, 1e-12)
+        t_sample += secs
+        per_fact += fc / rate
+        parts.append(f"nf [{lo},{min(hi, int(nf.max()) + 1)}): {idx.size} fronts, "
+                     f"{fc / F:.3f} of flops, {rate / 1e9:.2f} GFLOP/s")
     projected = t_order + n_factorizations * per_fact
+    model, ncpu = _cpu_info()
     return {
         "value": projected, "unit": "s (projected)", "cores": 1, "kind": "oracle",
-        "sample": (f"plain-C sparse LDL^T of the n={pencil.n} pencil at sigma={sigma:.6f}, stopped "
-                   f"after its first {st.flops_done:.3e} of {st.flops:.3e} flops (fronts in "
-                   f"postorder) in {t_all:.1f} s incl. {t_sym:.1f} s symbolic; rate "
-                   f"{rate / 1e9:.2f} GFLOP/s on 1 core; projected x{n_factorizations} "
-                   f"factorizations + ordering {t_order:.1f} s (solves and Lanczos not counted)"),
+        "host": f"{model}, {ncpu} logical CPUs",
+        "per_factorization_s": per_fact,
+        "sample": (f"oracle ordering {t_order:.1f} s and symbolic {t_sym:.1f} s of the n={pencil.n} "
+                   f"pencil timed whole; its front partial factorization timed on synthetic "
+                   f"fronts of the workload's shapes, {per_class} per size class "
+                   f"({t_sample:.1f} s of samples, largest fronts capped at {sample_flops:.1e} flops "
+                   f"of their first pivots): " + "; ".join(parts) +
+                   f"; projected x{n_factorizations} factorizations (assembly, extend-add, "
+                   f"solves and Lanczos not counted)"),
     }
 
 
@@ -184,8 +244,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n524k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-flops", type=float, default=1e10)
-    ap.add_argument("--profile-reps", type=int, default=3)
+    ap.add_argument("--profile-reps", type=int, default=5)
+    ap.add_argument("--skip", nargs="*", default=[], choices=["hbm", "fp32_ir", "c3a", "c3b"],
+                    help="extra legs to leave out")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="one factorization + a 1 GiB calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
@@ -278,10 +339,13 @@ def main():
             "factorizations_per_step": info["n_factorizations"],
             "stage1_steps": info["stage1_steps"], "bisection_steps": info["bisection_steps"],
             "si_steps": info["si_steps"],
+            "min_pivot_rel": info["min_pivot_rel"], "max_abs_l": info["max_abs_l"],
+            "weak_pivot_nudges": info["weak_pivot_nudges"],
             "t_task_s": info["t_task"][1:],
             "cold_pencil_create_s": t_cold,
             "ldlt_flops": ana["flops"],
             "ldlt_seconds": tot,
+            "ldlt_seconds_of": f"median of {args.profile_reps} event-timed factorizations",
             "ldlt_gflops": ldlt_gflops,
             "ldlt_frac_fp64_peak": ldlt_gflops / (PEAK_FP64_TFLOPS * 1e3),
         },
@@ -302,9 +366,117 @@ def main():
             "classes_ms": {k: statistics.median(pr[k]["seconds"] for pr in profs) * 1e3 for k in classes},
         },
     }
+
+    def leg(name, fn):
+        if name in args.skip:
+            return
+        t = time.perf_counter()
+        try:
+            out[name] = fn()
+        except Exception as e:            # report, keep the headline line
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"{name}: {time.perf_counter() - t:.1f} s: {json.dumps(out[name])[:300]}")
+
+    def hbm_leg():
+        # bandwidth of the solve and the SpMV at the shift-and-invert shift
+        F = P.factor(info["sigma_si"])
+        pr = F.profile_solve(10)
+        F.close()
+        return {
+            "solve": {"seconds": pr["solve_s"], "bytes": pr["solve_bytes"],
+                      "gbs": pr["solve_bytes"] / pr["solve_s"] / 1e9,
+                      "frac": pr["solve_bytes"] / pr["solve_s"] / 1e9 / PEAK_HBM_GBS},
+            "spmv_b": {"seconds": pr["spmv_b_s"], "bytes": pr["spmv_b_bytes"],
+                       "gbs": pr["spmv_b_bytes"] / pr["spmv_b_s"] / 1e9,
+                       "frac": pr["spmv_b_bytes"] / pr["spmv_b_s"] / 1e9 / PEAK_HBM_GBS},
+            "spmv_ab": {"seconds": pr["spmv_ab_s"], "bytes": pr["spmv_ab_bytes"],
+                        "gbs": pr["spmv_ab_bytes"] / pr["spmv_ab_s"] / 1e9,
+                        "frac": pr["spmv_ab_bytes"] / pr["spmv_ab_s"] / 1e9 / PEAK_HBM_GBS},
+            "peak_gbs": PEAK_HBM_GBS,
+            "bytes_are": "algorithmic (one read of the factor per sweep; CSR values, indices, vectors once)",
+        }
+
+    def fp32_leg():
+        # the same run with the shift-and-invert factor in FP32 + FP64 refinement
+        o32 = K.default_opts(start_vectors=pg.start_vectors(p.n), si_precision=K.KTH_FP32_IR)
+        P.eig(p.k, opts=o32, want_x=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        l32, _, i32 = P.eig(p.k, opts=o32, want_x=False)
+        torch.cuda.synchronize()
+        return {"time_s": time.perf_counter() - t, "lambda_k": l32, "abs_diff_vs_fp64": abs(l32 - lam),
+                "k_validated": i32["k_validated"], "rel_residual_normA": i32["rel_residual_normA"],
+                "si_steps": i32["si_steps"], "ir_steps": i32["ir_steps"],
+                "ir_fallback": i32["ir_fallback"], "t_si_factor_s": i32["t_task"][5],
+                "t_si_lanczos_s": i32["t_task"][6], "fp64_t_si_lanczos_s": info["t_task"][6]}
+
+    def c3a_leg():
+        # 64 shifts of the n = 131072 pencil per round, against one at a time and
+        # against sequential bisection to the same stopping rule
+        q = pg.workload("n131k")
+        Q = K.Pencil.from_pencilgen(ctx, q)
+        oq = K.default_opts(start_vectors=pg.start_vectors(q.n))
+        _, _, iq = Q.eig(q.k, opts=oq, want_x=False)
+        s1 = iq["stage1_steps"]
+        sl, su = sorted(iq["sigmas"][s1 - 2:s1]) if s1 >= 2 else (iq["sigma_lower"], iq["sigma_upper"])
+        sig = [sl + (su - sl) * (i + 1) / 65.0 for i in range(64)]
+        Q.inertia_batch(sig[:2])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        nb = Q.inertia_batch(sig)
+        t_batch = time.perf_counter() - t
+        t = time.perf_counter()
+        ns_ = [Q.nu(x) for x in sig]
+        t_single = time.perf_counter() - t
+        om = K.default_opts(start_vectors=pg.start_vectors(q.n), multisection=64)
+        Q.eig(q.k, opts=om, want_x=False)
+        t = time.perf_counter()
+        lm, _, im = Q.eig(q.k, opts=om, want_x=False)
+        t_ms_eig = time.perf_counter() - t
+        t = time.perf_counter()
+        l1, _, i1 = Q.eig(q.k, opts=oq, want_x=False)
+        t_bi_eig = time.perf_counter() - t
+        return {"workload": "n131k (n=131072), 64 equispaced interior shifts of the stage-1 interval",
+                "round_64_batched_s": t_batch, "round_64_one_at_a_time_s": t_single,
+                "counts_equal": list(map(int, nb)) == ns_,
+                "stage2_multisection64_s": im["t_task"][4], "stage2_rounds": im["bisection_steps"],
+                "stage2_bisection_s": i1["t_task"][4], "bisection_steps": i1["bisection_steps"],
+                "eig_multisection64_s": t_ms_eig, "eig_bisection_s": t_bi_eig,
+                "lambda_abs_diff": abs(lm - l1), "validated": im["k_validated"] == i1["k_validated"] == q.k}
+
+    def c3b_leg():
+        # 256 uneven pencils (n in [500, 8000]) in one batched call, against a loop
+        pens = pg.uneven_batch(count=256, seed=0)
+        t = time.perf_counter()
+        Ps = [K.Pencil.from_pencilgen(ctx, q) for q in pens]
+        t_create = time.perf_counter() - t
+        ks = [q.k for q in pens]
+        K.eig_batch(ctx, Ps[:8], ks[:8], want_x=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = K.eig_batch(ctx, Ps, ks, want_x=False)
+        t_batch = time.perf_counter() - t
+        t = time.perf_counter()
+        loop = [Pq.eig(kq, want_x=False)[0] for Pq, kq in zip(Ps, ks)]
+        t_loop = time.perf_counter() - t
+        ok = sum(r[0] == K.KTH_OK and r[3]["k_validated"] == kq for r, kq in zip(res, ks))
+        same = sum(r[1] == lq for r, lq in zip(res, loop))
+        for Pq in Ps:
+            Pq.close()
+        return {"pencils": len(pens), "n_range": [min(q.n for q in pens), max(q.n for q in pens)],
+                "batched_s": t_batch, "pencils_per_s": len(pens) / t_batch,
+                "loop_of_kth_eig_s": t_loop, "loop_pencils_per_s": len(pens) / t_loop,
+                "speedup": t_loop / t_batch, "validated": ok, "lambda_equal_to_loop": same,
+                "host_analysis_s": t_create,
+                "factorizations": sum(r[3]["n_factorizations"] for r in res)}
+
+    leg("hbm", hbm_leg)
+    leg("fp32_ir", fp32_leg)
+    leg("c3a", c3a_leg)
+    leg("c3b", c3b_leg)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)...")
-        out["cpu_baseline"] = cpu_baseline(p, sigma2, info["n_factorizations"], args.cpu_sample_flops)
+        out["cpu_baseline"] = cpu_baseline(p, info["n_factorizations"])
     print(json.dumps(out), flush=True)
 
 

@@ -235,6 +235,15 @@ kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double
  *   and written once, each operand row read once); [27] nu(sigma). */
 kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t nout);
 
+/* Measurement of the bandwidth-bound steps with a kept factor f: HIP events on the
+ * context stream around `reps` back-to-back solves (one pass: FP64, or an FP32
+ * factor unrefined), `reps` products B x, and `reps` fused products A x and B x.
+ * out (nout >= 6 doubles): [0] seconds per solve, [1] its algorithmic bytes
+ * (every entry of L read in the forward and in the backward sweep, 2 * 8 * nnz(L)
+ * for FP64, + 32 n for the vectors), [2] seconds per B x, [3] its bytes (12 nnz +
+ * 24 n), [4] seconds per fused A x, B x, [5] its bytes (20 nnz + 32 n). */
+kth_status kth_profile_solve(kth_factor_t f, int32_t reps, double* out, int32_t nout);
+
 /* Diagnostics: one v_mfma_f64_16x16x4 on device 0, zero accumulator; lane l of
  * the wavefront supplies A[l] and B[l] (64 doubles each) and result register r
  * of lane l lands in D[4 l + r] (256 doubles).  Host pointers.  Used by the

@@ -106,6 +106,7 @@ def lib() -> C.CDLL:
         "kth_eig_backward": ([vp, C.c_double, pd, C.c_double, pd, pd], C.c_int),
         "kth_debug_mfma_probe": ([pd, pd, pd], C.c_int),
         "kth_profile_factor": ([vp, C.c_double, pd, C.c_int32], C.c_int),
+        "kth_profile_solve": ([vp, C.c_int32, pd, C.c_int32], C.c_int),
         "kth_debug_mfma_probe_f32": ([C.POINTER(C.c_float)] * 3, C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -285,6 +286,14 @@ class Factor:
         _check(lib().kth_factor_stats(self.h, C.byref(n2), C.byref(md), C.byref(ml)),
                self.pencil.ctx.h)
         return dict(n2x2=n2.value, min_pivot_rel=md.value, max_abs_l=ml.value)
+
+    def profile_solve(self, reps: int = 10) -> dict:
+        """Event timing of solves and SpMV (see kth_profile_solve)."""
+        out = np.zeros(6)
+        _check(lib().kth_profile_solve(self.h, int(reps), _p(out, C.c_double), 6),
+               self.pencil.ctx.h)
+        return dict(solve_s=out[0], solve_bytes=out[1], spmv_b_s=out[2], spmv_b_bytes=out[3],
+                    spmv_ab_s=out[4], spmv_ab_bytes=out[5])
 
     def solve(self, r, refine: bool = True):
         """X = (A - sigma B)^{-1} R; refine=False applies an FP32 factor once."""

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/kth.h"
+#include "blas.hpp"
 #include "driver.hpp"
 #include "engine.hpp"
 
@@ -432,6 +433,54 @@ kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t n
       out[6 + 4 * c] = prof.bytes[c];
     }
     out[27] = (double)F.hs.neg;
+  });
+}
+
+kth_status kth_profile_solve(kth_factor_t f, int32_t reps, double* out, int32_t nout) {
+  if (!f || !out || nout < 6 || reps < 1) return KTH_EINVAL;
+  kth_pencil_s* pp = f->pen;
+  return guarded(&pp->ctx->c, [&] {
+    set_device(pp->ctx->c);
+    Pencil& P = pp->p;
+    Ctx* c = P.ctx;
+    hipStream_t st = c->stream;
+    DBuf<double> b, x, y;
+    b.alloc(c, P.n);
+    x.alloc(c, P.n);
+    y.alloc(c, P.n);
+    // right-hand side e_1 (the sweeps read the whole factor whatever the vector)
+    KTH_HIP(hipMemsetAsync(b.get(), 0, sizeof(double) * P.n, st));
+    launch_set_scalar(b.get(), 1.0, st);
+    solve_enqueue_f(P, f->f, b.get(), x.get());   // warm
+    hipEvent_t e[6];
+    for (auto& q : e) KTH_HIP(hipEventCreate(&q));
+    KTH_HIP(hipEventRecord(e[0], st));
+    for (int r = 0; r < reps; r++) solve_enqueue_f(P, f->f, b.get(), x.get());
+    KTH_HIP(hipEventRecord(e[1], st));
+    for (int r = 0; r < reps; r++)
+      spmv2(P.n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), x.get(), nullptr, y.get(), st);
+    KTH_HIP(hipEventRecord(e[2], st));
+    KTH_HIP(hipEventRecord(e[3], st));
+    for (int r = 0; r < reps; r++)
+      spmv2(P.n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), x.get(), y.get(), b.get(), st);
+    KTH_HIP(hipEventRecord(e[4], st));
+    c->sync();
+    float ms0 = 0, ms1 = 0, ms2 = 0;
+    KTH_HIP(hipEventElapsedTime(&ms0, e[0], e[1]));
+    KTH_HIP(hipEventElapsedTime(&ms1, e[1], e[2]));
+    KTH_HIP(hipEventElapsedTime(&ms2, e[3], e[4]));
+    for (auto& q : e) (void)hipEventDestroy(q);
+    const double n = (double)P.n, nnz = (double)P.nnz;
+    const double tsz = f->f.prec == KTH_FP64 ? 8.0 : 4.0;
+    for (int q = 0; q < nout; q++) out[q] = 0.0;
+    out[0] = ms0 * 1e-3 / reps;
+    out[1] = 2.0 * tsz * (double)P.S.nnz_l + 32.0 * n;   // L read forward and backward; b, x, work vectors
+    out[2] = ms1 * 1e-3 / reps;
+    out[3] = 12.0 * nnz + 24.0 * n;                      // B x: values + columns, row pointers, x, y
+    if (nout > 5) {
+      out[4] = ms2 * 1e-3 / reps;
+      out[5] = 20.0 * nnz + 32.0 * n;                    // A x and B x together
+    }
   });
 }
 
