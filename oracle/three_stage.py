@@ -134,6 +134,52 @@ def stage2(k, sl, su, nl, nu_, nu_of, log, m_max=20, tau_len=0.0):
     return sl, su, nl, nu_, steps
 
 
+def interp_shift(k, sl, su, nl, nu_, m_max):
+    """The next shift of the interpolating stage 2 (a bracketing root-finder on
+    the counting function, Section 2.1 and Section 5 name such methods as
+    alternatives to bisection).  nu(sigma) is modelled as linear between the
+    bracket ends; the shift aims at the count that would bring the farther end
+    to within m_max / 2 of k: k - m_max/2 for the lower end, k + m_max/2 - 1 for
+    the upper one, plus 1/2 to land inside the count's step.  The fraction of
+    the bracket is kept inside [1/64, 63/64]."""
+    if (k - nl) >= (nu_ - k):
+        c = k - m_max / 2.0 + 0.5
+    else:
+        c = k + m_max / 2.0 - 1.0 + 0.5
+    t = (c - nl) / (nu_ - nl)
+    t = min(max(t, 1.0 / 64.0), 63.0 / 64.0)
+    return sl + t * (su - sl)
+
+
+def stage2_interp(k, sl, su, nl, nu_, nu_of, log, m_max=20, tau_len=0.0):
+    """Stage 2 with a safeguarded interpolating root-finder instead of the
+    midpoint: the shift comes from interp_shift, except that after the same end
+    of the bracket moved on two consecutive interpolated steps the next shift is
+    the midpoint (a bisection step), which bounds the worst case.  Same stopping
+    rule as Alg. 1' (at least one step; stop at nu_u - nu_l <= m_max, or below
+    tau_len)."""
+    steps = 0
+    moved = []          # "l" / "u" per interpolated step since the last bisection
+    while True:
+        bisect = len(moved) >= 2 and moved[-1] == moved[-2]
+        sig = 0.5 * (sl + su) if bisect else interp_shift(k, sl, su, nl, nu_, m_max)
+        nu = nu_of(sig)
+        log.append((sig, nu))
+        steps += 1
+        if k <= nu:
+            su, nu_ = sig, nu
+            end = "u"
+        else:
+            sl, nl = sig, nu
+            end = "l"
+        moved = [] if bisect else moved + [end]
+        if nu_ - nl <= m_max:
+            break
+        if tau_len > 0 and (su - sl) < tau_len:
+            break
+    return sl, su, nl, nu_, steps
+
+
 def alg1_bisection(k, sl, su, nu_of, tau=None, rel_tau=None):
     """Alg. 1: plain spectral bisection until the interval is shorter than tau
     (absolute), or, as in the straightforward variant of Section 4.3.2, until
@@ -232,8 +278,9 @@ def stage3(pencil, k, sl, su, nl, nu_, A, B, v0, tau_res=1e-10, tau_diff=1e-10,
 
 
 def kth_eig(pencil, k: int | None = None, m_max=20, tau_res=1e-10, tau_diff=1e-10,
-            tau_len=0.0, seed=0, max_iter=500) -> Result:
-    """Alg. 4 over the oracle's sparse LDL^T."""
+            tau_len=0.0, seed=0, max_iter=500, root_finder="bisection") -> Result:
+    """Alg. 4 over the oracle's sparse LDL^T.  root_finder: "bisection" (Alg. 1')
+    or "interp" (stage2_interp) for stage 2."""
     k = pencil.k if k is None else k
     P = osp.prepare(pencil)
     A, B = pencil.A(), pencil.B()
@@ -253,7 +300,12 @@ def kth_eig(pencil, k: int | None = None, m_max=20, tau_res=1e-10, tau_diff=1e-1
         return osp.nu(P, s)
 
     sl, su, nl, nu_, s1 = stage1(pencil, k, P, A, B, Bfac, v0s, nu_of, log)
-    sl, su, nl, nu_, s2 = stage2(k, sl, su, nl, nu_, nu_of, log, m_max, tau_len)
+    if root_finder == "interp":
+        sl, su, nl, nu_, s2 = stage2_interp(k, sl, su, nl, nu_, nu_of, log, m_max, tau_len)
+    elif root_finder == "bisection":
+        sl, su, nl, nu_, s2 = stage2(k, sl, su, nl, nu_, nu_of, log, m_max, tau_len)
+    else:
+        raise ValueError(f"unknown root finder {root_finder!r}")
     nfac[0] += 1
     lam, x, sj, sig, ib, ir, idf = stage3(P, k, sl, su, nl, nu_, A, B, v0s[1], tau_res,
                                           tau_diff, max_iter)

@@ -22,7 +22,7 @@ the GPU library.  Each job writes one JSON file next to this script:
                                   the dense oracle (Cholesky reduction, eigenvalues)
 
 Usage: python tests/golden/make_golden.py inertia n131k -3.0
-       python tests/golden/make_golden.py three_stage n131k
+       python tests/golden/make_golden.py three_stage n131k [bisection|interp]
        python tests/golden/make_golden.py kth_oracle n524k [workers]
        python tests/golden/make_golden.py batch_dense 256
 """
@@ -186,15 +186,18 @@ def main(argv):
                    seconds=time.perf_counter() - t, source="oracle.sparse.ldlt_stats")
         path = os.path.join(HERE, f"inertia_{cfg}_{sigma:+.3f}.json")
     elif job == "three_stage":
+        rf = argv[2] if len(argv) > 2 else "bisection"
         t = time.perf_counter()
-        r = o3.kth_eig(p)
+        r = o3.kth_eig(p, root_finder=rf)
         out = dict(config=cfg, n=p.n, k=p.k, lam=r.lam, sigma_lower=r.sigma_lower,
                    sigma_upper=r.sigma_upper, nu_lower=r.nu_lower, nu_upper=r.nu_upper,
                    sigmas=r.sigmas, nus=r.nus, rel_residual=r.rel_residual,
                    norm_a_inf=od.norm_inf(p), stage1_steps=r.stage1_steps,
                    bisection_steps=r.bisection_steps, si_steps=r.si_steps,
-                   seconds=time.perf_counter() - t, source="oracle.three_stage.kth_eig")
-        path = os.path.join(HERE, f"three_stage_{cfg}.json")
+                   root_finder=rf, seconds=time.perf_counter() - t,
+                   source="oracle.three_stage.kth_eig")
+        path = os.path.join(HERE, f"three_stage_{cfg}.json" if rf == "bisection"
+                            else f"three_stage_{cfg}_{rf}.json")
     else:
         raise SystemExit("unknown job " + job)
     with open(path, "w") as f:

@@ -155,3 +155,62 @@ def test_straightforward_bisection_footnote_count():
                                          rel_tau=1e-14)
     assert 47 <= steps <= 49
     assert abs(est - lam_k) < 1e-14
+
+
+def _diag_count(eigs):
+    eigs = np.sort(np.asarray(eigs, dtype=float))
+    return lambda s: int(np.searchsorted(eigs, s, side="left"))
+
+
+def test_interp_stage2_linear_count_lands_in_two_steps():
+    # eigenvalues 1..n: the count is linear between the bracket ends up to its
+    # unit steps, so each interpolated shift lands within one of its target count:
+    # the first brings the lower end to k - m/2, the second the upper to k + m/2 - 1
+    n, k, m = 1000, 400, 20
+    nu_of = _diag_count(np.arange(1, n + 1))
+    log = []
+    sl, su, nl, nu_, steps = o3.stage2_interp(k, 0.5, n + 0.5, 0, n, nu_of, log, m_max=m)
+    assert steps == 2
+    assert k - m // 2 - 1 <= nl < k <= nu_ <= k + m // 2
+    assert nu_ - nl <= m
+    # the same bracket by bisection takes ceil(log2(n / m)) steps at least
+    log2 = []
+    assert o3.stage2(k, 0.5, n + 0.5, 0, n, nu_of, log2, m_max=m)[4] >= math.ceil(math.log2(n / m))
+
+
+def test_interp_stage2_cluster_falls_back_to_bisection():
+    # 1000 eigenvalues piled into [50, 50.001] among 1..100: the linear model is
+    # badly wrong, the safeguard's midpoint steps still isolate k
+    eigs = np.concatenate([np.arange(1.0, 101.0), 50.0 + np.linspace(1e-4, 1e-3, 1000)])
+    nu_of = _diag_count(eigs)
+    lam = np.sort(eigs)
+    for k in (30, 300, 1060):
+        log = []
+        sl, su, nl, nu_, steps = o3.stage2_interp(k, 0.5, 100.5, 0, eigs.size, nu_of, log)
+        assert nl == nu_of(sl) and nu_ == nu_of(su)
+        assert nl < k <= nu_ and nu_ - nl <= 20
+        assert sl < lam[k - 1] < su
+        log2 = []
+        assert steps <= 3 * o3.stage2(k, 0.5, 100.5, 0, eigs.size, nu_of, log2)[4]
+
+
+@pytest.mark.parametrize("which", ["tiny", "fem"])
+def test_three_stage_interp_matches_dense(which):
+    if which == "tiny":
+        p = pg.tb_supercell((4, 4, 4), seed=0)
+        lam = od.eigvals(p)
+    else:
+        N, w = (9, 10, 11), (1.0, 1.4, 0.8)
+        p = pg.fem_tensor(N, w)
+        lam = fem_eigs(N, w)
+    k = p.k
+    nA = od.norm_inf(p)
+    rb = o3.kth_eig(p, k)
+    ri = o3.kth_eig(p, k, root_finder="interp")
+    assert ri.k_validated == k
+    assert abs(ri.lam - lam[k - 1]) <= 1e-10 * nA
+    assert ri.nu_lower == od.nu(lam, ri.sigma_lower) and ri.nu_upper == od.nu(lam, ri.sigma_upper)
+    assert ri.nu_lower < k <= ri.nu_upper and ri.nu_upper - ri.nu_lower <= 20
+    for s, v in zip(ri.sigmas, ri.nus):
+        assert v == od.nu(lam, s)
+    assert ri.bisection_steps < rb.bisection_steps
