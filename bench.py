@@ -245,7 +245,12 @@ def main():
     ap.add_argument("--workload", default="n524k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=5)
-    ap.add_argument("--skip", nargs="*", default=[], choices=["hbm", "fp32_ir", "c3a", "c3b"],
+    ap.add_argument("--m-max", type=int, default=0,
+                    help="stage-2 stopping count (0: chosen by the library's cost model)")
+    ap.add_argument("--root-finder", type=int, default=1, choices=[0, 1],
+                    help="stage 2: 0 bisection (Alg. 1'), 1 safeguarded interpolation")
+    ap.add_argument("--skip", nargs="*", default=[],
+                    choices=["stage2_other", "hbm", "fp32_ir", "c3a", "c3b"],
                     help="extra legs to leave out")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="one factorization + a 1 GiB calibration copy, for rocprofv3 --pmc")
@@ -281,7 +286,8 @@ def main():
     t_cold = time.perf_counter() - t0
     ana = K.kth_analyze(p.rowptr, p.col)
     log(f"pencil ready in {t_cold:.2f} s (analysis flops {ana['flops']:.3e}, max front {ana['max_front']:.0f})")
-    opts = K.default_opts(start_vectors=pg.start_vectors(p.n))
+    opts = K.default_opts(start_vectors=pg.start_vectors(p.n), root_finder=args.root_finder,
+                          m_max=args.m_max)
 
     for w in range(args.warmup):
         lam, _, info = P.eig(p.k, opts=opts, want_x=False)
@@ -339,6 +345,9 @@ def main():
             "factorizations_per_step": info["n_factorizations"],
             "stage1_steps": info["stage1_steps"], "bisection_steps": info["bisection_steps"],
             "si_steps": info["si_steps"],
+            "m_max_used": info["m_max_used"],
+            "stage2": "bisection (Alg. 1')" if args.root_finder == 0 else
+                      "safeguarded interpolation of the count (root_finder=1)",
             "min_pivot_rel": info["min_pivot_rel"], "max_abs_l": info["max_abs_l"],
             "weak_pivot_nudges": info["weak_pivot_nudges"],
             "t_task_s": info["t_task"][1:],
@@ -396,9 +405,25 @@ def main():
             "bytes_are": "algorithmic (one read of the factor per sweep; CSR values, indices, vectors once)",
         }
 
+    def stage2_leg():
+        # the same run with the other stage-2 rule
+        other = 1 - args.root_finder
+        oo = K.default_opts(start_vectors=pg.start_vectors(p.n), root_finder=other,
+                            m_max=20 if other == 0 else args.m_max)
+        P.eig(p.k, opts=oo, want_x=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lo, _, io = P.eig(p.k, opts=oo, want_x=False)
+        torch.cuda.synchronize()
+        return {"root_finder": other, "m_max": oo.m_max, "time_s": time.perf_counter() - t, "lambda_k": lo,
+                "abs_diff": abs(lo - lam), "k_validated": io["k_validated"],
+                "factorizations": io["n_factorizations"], "stage2_steps": io["bisection_steps"],
+                "t_stage2_s": io["t_task"][4]}
+
     def fp32_leg():
         # the same run with the shift-and-invert factor in FP32 + FP64 refinement
-        o32 = K.default_opts(start_vectors=pg.start_vectors(p.n), si_precision=K.KTH_FP32_IR)
+        o32 = K.default_opts(start_vectors=pg.start_vectors(p.n), si_precision=K.KTH_FP32_IR,
+                             root_finder=args.root_finder, m_max=args.m_max)
         P.eig(p.k, opts=o32, want_x=False)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -470,6 +495,7 @@ def main():
                 "host_analysis_s": t_create,
                 "factorizations": sum(r[3]["n_factorizations"] for r in res)}
 
+    leg("stage2_other", stage2_leg)
     leg("hbm", hbm_leg)
     leg("fp32_ir", fp32_leg)
     leg("c3a", c3a_leg)

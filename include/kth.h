@@ -155,7 +155,13 @@ kth_status kth_solve_noalloc(kth_factor_t f, int32_t nrhs, const double* r, int6
 kth_status kth_factor_stats(kth_factor_t f, int64_t* n2x2, double* min_pivot_rel, double* max_abs_l);
 
 typedef struct {
-  int64_t m_max;          /* bisection stops at <= m_max eigenvalues in the interval (20)    */
+  int64_t m_max;          /* stage 2 stops at <= m_max eigenvalues in the interval (20, the
+                             paper's value); 0: a cost model picks it (kth_info.m_max_used):
+                             2 with root_finder = 1, whose last shifts land within about a
+                             count of their targets; with bisection 2 t_f / (2.6 x 1.15 t_s)
+                             clamped to [2, 20], from the measured time t_f of a stage-1
+                             factorization and t_s of a stage-1 solve (Alg. 3 takes about
+                             2.6 m + 8 steps of about 1.15 solves for m eigenvalues)       */
   double tau_res;         /* relative residual tolerance of Alg. 3 (1e-10)                    */
   double tau_diff;        /* relative difference tolerance of Alg. 3 (1e-10)                  */
   double tau_len;         /* bisection also stops below this interval length (0: off)        */
@@ -169,6 +175,14 @@ typedef struct {
   double ir_tol;          /* FP32 shift-and-invert solves: target backward error (0: 4 eps64) */
   int32_t batch_workers;  /* kth_eig_batch: pencils solved concurrently, each on its own
                              streams (0: 8; 1: one after another on the context stream) */
+  int32_t root_finder;    /* stage 2: 0 bisection (Alg. 1'); 1 safeguarded interpolation of
+                             the eigenvalue count (a bracketing root-finder, Section 2.1):
+                             each shift aims, by linear interpolation of nu between the
+                             bracket ends, at the count k - m_max/2 (lower end) or
+                             k + m_max/2 - 1 (upper end), whichever end is farther from k,
+                             at a fraction of the bracket within [1/64, 63/64]; after the
+                             same end moved on two consecutive such steps the next shift
+                             is the midpoint.  Same stopping rule.  Needs multisection = 1. */
 } kth_opts;
 
 typedef struct {
@@ -197,6 +211,8 @@ typedef struct {
                                  multiplier above 1e8 (restricted pivoting, Section 2.1)     */
   int32_t weak_pivot_kept;    /* counts accepted with a weak nonzero pivot after three moves   */
   int32_t stage1_restarts;    /* stage-1 Lanczos restarts after a breakdown (beta = 0)         */
+  int32_t pad0;
+  int64_t m_max_used;         /* stage-2 stopping count in effect (opts.m_max, or the model's) */
 } kth_info;
 
 void kth_opts_default(kth_opts* o);

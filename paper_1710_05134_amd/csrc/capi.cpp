@@ -60,7 +60,7 @@ kth_status guarded(Ctx* c, F&& fn) {
 void set_device(Ctx& c) { KTH_HIP(hipSetDevice(c.device)); }
 
 void check_opts(const kth_opts& o) {
-  if (o.m_max < 1) throw Error(KTH_EINVAL, "m_max must be >= 1");
+  if (o.m_max < 0) throw Error(KTH_EINVAL, "m_max must be >= 0 (0: automatic)");
   if (!(o.tau_res > 0) || !(o.tau_diff > 0)) throw Error(KTH_EINVAL, "tolerances must be > 0");
   if (!(o.tau_len >= 0)) throw Error(KTH_EINVAL, "tau_len must be >= 0");
   if (o.max_lanczos < 1) throw Error(KTH_EINVAL, "max_lanczos must be >= 1");
@@ -70,6 +70,9 @@ void check_opts(const kth_opts& o) {
     throw Error(KTH_EINVAL, "unknown si_precision");
   if (!(o.ir_tol >= 0) || !std::isfinite(o.ir_tol)) throw Error(KTH_EINVAL, "ir_tol must be >= 0");
   if (o.batch_workers < 0 || o.batch_workers > 64) throw Error(KTH_EINVAL, "batch_workers must be in [0, 64]");
+  if (o.root_finder != 0 && o.root_finder != 1) throw Error(KTH_EINVAL, "root_finder must be 0 or 1");
+  if (o.root_finder == 1 && o.multisection != 1)
+    throw Error(KTH_EINVAL, "the interpolating root-finder takes one shift per step (multisection = 1)");
 }
 
 void ctx_release(kth_ctx_s* c) {

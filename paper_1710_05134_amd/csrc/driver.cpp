@@ -205,6 +205,40 @@ int64_t nu_checked(Pencil& P, double& sigma, double nudge, Shifts& log, int64_t*
   throw Error(KTH_ESINGULAR, "repeated zero pivots near sigma");
 }
 
+// Next shift of the interpolating stage 2 (a bracketing root-finder on the
+// eigenvalue count; Section 2.1 and Section 5 name such methods as alternatives
+// to bisection): the count is modelled as linear between the bracket ends and the
+// shift aims at the count that brings the farther end to within m_max / 2 of k
+// (k - m_max/2 below, k + m_max/2 - 1 above, + 1/2 to land inside the count's
+// step), at a fraction of the bracket kept inside [1/64, 63/64].  The arithmetic
+// is written out operation by operation, uncontracted, so the shifts are the same
+// doubles as the oracle's.
+double interp_shift(int64_t k, double sl, double su, int64_t nl, int64_t nu_, int64_t m_max) {
+#pragma clang fp contract(off)
+  double c;
+  if ((k - nl) >= (nu_ - k)) c = (double)k - (double)m_max / 2.0 + 0.5;
+  else c = (double)k + (double)m_max / 2.0 - 1.0 + 0.5;
+  double t = (c - (double)nl) / (double)(nu_ - nl);
+  t = std::min(std::max(t, 1.0 / 64.0), 63.0 / 64.0);
+  return sl + t * (su - sl);
+}
+
+// Stage-2 stopping count from measured costs (Section 3.4 and Section 5 leave
+// m_max, which trades bisection steps against Lanczos steps, to tuning).  The
+// validated shift-and-invert iteration of Alg. 3 takes about 2.6 m + 8 steps for
+// m eigenvalues in the interval (measured on the tight-binding workloads), each
+// step about 1.15 solves.  Bisection halves m for one more factorization, which
+// pays while 2.6 (m / 2) t_step > t_fact, i.e. down to m = 2 t_fact / (2.6 t_step).
+// The interpolating root-finder lands its last shifts within about one count of
+// their targets, so narrowing costs it no extra steps down to m_max = 2 (the
+// bracket [lambda_{k-1}, lambda_{k+1}]); it takes 2.  Clamped to [2, 20].
+int64_t auto_m_max(int root_finder, double t_fact, double t_solve) {
+  if (root_finder == 1) return 2;
+  if (!(t_fact > 0) || !(t_solve > 0)) return 20;
+  const double m = 2.0 * t_fact / (2.6 * 1.15 * t_solve);
+  return std::min<int64_t>(20, std::max<int64_t>(2, (int64_t)std::lround(m)));
+}
+
 }  // namespace
 
 void numeric_factor(Pencil& P, NumFactor& F, double sigma, kth_precision prec) {
@@ -424,6 +458,10 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   double sl, su;
   int64_t nl, nu_;
   int s1 = 0, s2 = 0, s1_restarts = 0;
+  // cost model of the stage-2 stopping count (opts.m_max = 0): measured time of
+  // one factorization and of one solve in stage 1
+  double t_fact_meas = 0, t_solve_meas = 0;
+  int64_t m_eff = o.m_max;
   if (o.warm_interval && o.warm_counts) {
     sl = o.warm_interval[0];
     su = o.warm_interval[1];
@@ -449,7 +487,16 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
         // A v_j, alpha_j, w = B^{-1} A v_j
         spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.v(j - 1), W.ya.get(), nullptr, st);
         al.push_back(dot_dev(W, W.v(j - 1), W.ya.get()));
-        solve_enqueue_f(P, FB, W.ya.get(), W.w.get());
+        if (j == 1 && o.m_max == 0 && o.root_finder == 0) {
+          // time of one solve with a factor of the pencil's structure (cost model)
+          c->sync();
+          const double ts0 = now_s();
+          solve_enqueue_f(P, FB, W.ya.get(), W.w.get());
+          c->sync();
+          t_solve_meas = now_s() - ts0;
+        } else {
+          solve_enqueue_f(P, FB, W.ya.get(), W.w.get());
+        }
         KTH_HIP(hipMemcpyAsync(W.Bw.get(), W.ya.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         for (int pass = 0; pass < 2; pass++) {   // CGS2 in the B inner product: h = V^T (B w)
           multidot(n, j, W.V.get(), n, W.Bw.get(), W.partial.get(), W.h.get(), 1.0, st);
@@ -467,7 +514,8 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
         double sig = (k <= nu_prev) ? th[0] : th[j - 1];
         double tf = now_s();
         int64_t nu = nu_checked(P, sig, 1e-12 * std::max(nA, 1.0), log, &nfac);
-        t_task[3] += now_s() - tf;
+        t_fact_meas = now_s() - tf;
+        t_task[3] += t_fact_meas;
         s1 = j;
         if (j != 1 && ((nu < k && k <= nu_prev) || (nu_prev < k && k <= nu))) {
           sl = std::min(sig_prev, sig);
@@ -494,12 +542,26 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
     // ---- stage 2: Alg. 1' (repeat-until: at least one bisection step) ----
     double tb = now_s();
     const int ms = std::max(1, o.multisection);
+    m_eff = o.m_max > 0 ? o.m_max : auto_m_max(o.root_finder, t_fact_meas, t_solve_meas);
+    // interpolating stage 2: the same end of the bracket moving on two consecutive
+    // interpolated steps makes the next step a bisection (bounds the worst case)
+    char moved[2] = {0, 0};
+    int nmoved = 0;
     while (true) {
       if (ms == 1) {
-        double sig = 0.5 * (sl + su);
+        const bool bisect = o.root_finder == 0 || (nmoved >= 2 && moved[0] == moved[1]);
+        double sig = bisect ? 0.5 * (sl + su) : interp_shift(k, sl, su, nl, nu_, m_eff);
         int64_t nu = nu_checked(P, sig, 1e-3 * (su - sl), log, &nfac);
         s2++;
+        const char end = k <= nu ? 'u' : 'l';
         if (k <= nu) { su = sig; nu_ = nu; } else { sl = sig; nl = nu; }
+        if (bisect) {
+          nmoved = 0;
+        } else {
+          moved[0] = moved[1];
+          moved[1] = end;
+          nmoved++;
+        }
       } else {
         std::vector<double> sg(ms);
         std::vector<int64_t> cnt(ms), zc(ms);
@@ -526,7 +588,7 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
         }
         sl = nsl; su = nsu; nl = nnl; nu_ = nnu;
       }
-      if (nu_ - nl <= o.m_max) break;
+      if (nu_ - nl <= m_eff) break;
       if (o.tau_len > 0 && (su - sl) < o.tau_len) break;
       if (s2 > 200) throw Error(KTH_ECLUSTER, "bisection did not isolate a small interval");
     }
@@ -744,6 +806,7 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   info->weak_pivot_nudges = log.nudges;
   info->weak_pivot_kept = log.weak_kept;
   info->stage1_restarts = s1_restarts;
+  info->m_max_used = m_eff;
   info->n_factorizations = nfac;
   info->flops_factor = P.S.flops;
   for (int q = 0; q < 7; q++) info->t_task[q] = t_task[q];
