@@ -50,6 +50,7 @@ class Result:
     nus: list
     rel_residual: float   # ||(A - lam B) x||_2 / ||x||_2 with explicit products
     n_factorizations: int
+    si_block: int = 1     # block size of the shift-and-invert Lanczos that validated
 
 
 class NoConvergence(RuntimeError):
@@ -277,10 +278,171 @@ def stage3(pencil, k, sl, su, nl, nu_, A, B, v0, tau_res=1e-10, tau_diff=1e-10,
     raise NoConvergence("SI Lanczos did not converge")
 
 
+def _b_orthonormalize(X, BX):
+    """X R^{-1}, BX R^{-1} with X^T B X = R^T R (Cholesky), twice (CholQR2), and
+    the total factor R (upper triangular)."""
+    Rt = np.eye(X.shape[1])
+    for _ in range(2):
+        G = X.T @ BX
+        G = 0.5 * (G + G.T)
+        try:
+            R = np.linalg.cholesky(G).T
+        except np.linalg.LinAlgError:
+            raise NoConvergence("block Lanczos: the new block is rank deficient")
+        X = np.linalg.solve(R.T, X.T).T
+        BX = np.linalg.solve(R.T, BX.T).T
+        Rt = R @ Rt
+    return X, BX, Rt
+
+
+def _components(lam, eta, asc):
+    """Groups of consecutive (ascending) Ritz values whose closed bounds
+    [lam - eta, lam + eta] overlap."""
+    comps, cur = [], [asc[0]]
+    for a, b in zip(asc[:-1], asc[1:]):
+        if lam[a] + eta[a] >= lam[b] - eta[b]:
+            cur.append(b)
+        else:
+            comps.append(cur)
+            cur = [b]
+    comps.append(cur)
+    return comps
+
+
+def stage3_block(pencil, k, sl, su, nl, nu_, A, B, V0, tau_res=1e-10, tau_diff=1e-10,
+                 max_iter=500, factor=None, scale=None):
+    """Block shift-and-invert Lanczos for an interval that may hold multiple or
+    clustered eigenvalues (Section 3.4 names this modification; block size p =
+    V0.shape[1]).  With V = B^{-1} V~ kept B-orthonormal and V~ = B V:
+        (A - sigma B)^{-1} B V_j = V_j T_j + V_{j+1} B_j E_j^T,
+    T_j block tridiagonal (diagonal blocks A_i, subdiagonal blocks B_i upper
+    triangular from the B-orthonormalisation of each new block).  For a Ritz pair
+    (theta, y) of T_j: lambda = sigma + 1/theta, x_2 = theta V_j y + V_{j+1} B_j
+    E_j^T y = (A - sigma B)^{-1} V~_j y, residual (A - lambda B) x_2 = -V~_{j+1} s with
+    s = B_j E_j^T y / theta, so Prop. 3 holds with |s| replaced by ||s||_2.
+    Validation (Alg. 3 modified for multiplicity): the m pairs of largest |theta|;
+    every bound inside [sigma_l, sigma_u); bounds that overlap form a cluster C,
+    for which the B-orthonormal Ritz vectors V_j Y_C of the operator
+    (A - sigma B)^{-1} B (self-adjoint in the B inner product) have residual norm
+    rho = ||B_j E_j^T Y_C||_2, so (Kahan's theorem) |C| eigenvalues of the operator
+    lie within rho of the theta's, i.e. within rho / (|theta| (|theta| - rho)) of
+    the lambda's; cluster intervals and single bounds must be pairwise disjoint,
+    which accounts for all m eigenvalues of the interval.  Residual test per pair;
+    difference test per single pair as in Alg. 3, per cluster on its eigenvalues
+    (|lambda^(j) - lambda^(j-1)| <= tau_diff max(1, |lambda|), same cluster shape).
+    The bounds hold for the operator as applied; the factor's solves carry a
+    backward error of order eps ||A - sigma B||, so bounds and cluster radii are
+    not taken below 64 eps scale (scale = ||A||_inf + |sigma| ||B||_inf): the two
+    computed copies of a multiple eigenvalue then stay one cluster."""
+    l = k - nl
+    m = nu_ - nl
+    sigma = 0.5 * (sl + su)
+    F = factor if factor is not None else osp.Factor(pencil, sigma)
+    p = V0.shape[1]
+    if scale is None:
+        scale = (np.abs(A).sum(axis=1).max() + abs(sigma) * np.abs(B).sum(axis=1).max())
+    floor = 64.0 * np.finfo(float).eps * float(scale)
+    X, BX, _ = _b_orthonormalize(V0.copy(), B @ V0)
+    V, Vt, Ad, Bd = [X], [BX], [], []
+    prev = None
+    it_bound = it_res = it_diff = 0
+    for j in range(1, max_iter + 1):
+        W = np.column_stack([F.solve(Vt[-1][:, c]) for c in range(p)])
+        BW = B @ W
+        Vm, Vtm = np.hstack(V), np.hstack(Vt)
+        H = Vtm.T @ W
+        Ad.append(0.5 * (H[-p:] + H[-p:].T))
+        W -= Vm @ H
+        BW -= Vtm @ H
+        H2 = Vtm.T @ W
+        W -= Vm @ H2
+        BW -= Vtm @ H2
+        Wn, BWn, Rn = _b_orthonormalize(W, BW)
+        if j * p >= m:
+            T = np.zeros((j * p, j * p))
+            for i in range(j):
+                T[i * p:(i + 1) * p, i * p:(i + 1) * p] = Ad[i]
+                if i + 1 < j:
+                    T[(i + 1) * p:(i + 2) * p, i * p:(i + 1) * p] = Bd[i]
+                    T[i * p:(i + 1) * p, (i + 1) * p:(i + 2) * p] = Bd[i].T
+            th, Y = np.linalg.eigh(T)
+            sel = np.array(sorted(range(j * p), key=lambda i: (-abs(th[i]), -th[i]))[:m])
+            ts = th[sel]
+            lam = sigma + 1.0 / ts
+            Yl = Y[-p:, sel]
+            S = (Rn @ Yl) / ts
+            sn = np.linalg.norm(S, axis=0)
+            eta = np.maximum((1.0 / np.abs(ts)) * sn / np.sqrt(1.0 + sn * sn), floor)
+            X = Vm @ (Y[:, sel] * ts) + Wn @ (Rn @ Yl)
+            incl = bool(np.all(lam - eta >= sl) and np.all(lam + eta < su))
+            asc = np.argsort(lam, kind="stable")
+            comps = _components(lam, eta, asc)
+            ivals, ok = [], incl
+            for C in comps:
+                if len(C) == 1:
+                    q = C[0]
+                    ivals.append((lam[q] - eta[q], lam[q] + eta[q]))
+                    continue
+                rho = float(np.linalg.norm(Rn @ Yl[:, C], 2))
+                tc = np.abs(ts[C])
+                if rho >= tc.min():
+                    ok = False
+                    break
+                eps = np.maximum(rho / (tc * (tc - rho)), floor)
+                ivals.append((float(np.min(lam[C] - eps)), float(np.max(lam[C] + eps))))
+            if ok:
+                ok = all(lo >= sl and hi < su for lo, hi in ivals) and \
+                    all(ivals[i][1] < ivals[i + 1][0] for i in range(len(ivals) - 1))
+            xn = np.linalg.norm(X, axis=0)
+            rres = np.linalg.norm(BWn @ S, axis=0) / xn
+            res_ok = bool(np.all(rres < tau_res))
+            shape = tuple(len(C) for C in comps)
+            Xa = X[:, asc] / xn[asc]
+            la = lam[asc]
+            diff_ok = False
+            if prev is not None and prev[2] == shape:
+                pX, pl, _ = prev
+                diff_ok, pos = True, 0
+                for c in shape:
+                    if c == 1:
+                        sg = 1.0 if np.dot(Xa[:, pos], pX[:, pos]) >= 0 else -1.0
+                        diff_ok &= bool(np.linalg.norm(sg * Xa[:, pos] - pX[:, pos]) < tau_diff)
+                    else:
+                        seg = slice(pos, pos + c)
+                        diff_ok &= bool(np.all(np.abs(la[seg] - pl[seg])
+                                               <= tau_diff * np.maximum(1.0, np.abs(la[seg]))))
+                    pos += c
+            prev = (Xa, la, shape)
+            if ok and not it_bound:
+                it_bound = j
+            if res_ok and not it_res:
+                it_res = j
+            if diff_ok and not it_diff:
+                it_diff = j
+            if ok and res_ok and diff_ok:
+                return (float(la[l - 1]), X[:, asc[l - 1]].copy(), j, sigma, it_bound, it_res,
+                        it_diff)
+        V.append(Wn)
+        Vt.append(BWn)
+        Bd.append(Rn)
+    raise NoConvergence("block SI Lanczos did not converge")
+
+
+def block_start(n, p, seed=0):
+    """Start block of the block shift-and-invert Lanczos: column 0 is row 1 of
+    pencilgen.start_vectors (the single-vector start), columns 1.. rows 4.."""
+    sv = pencilgen.start_vectors(n, seed=seed, count=max(4, p + 3))
+    return np.column_stack([sv[1]] + [sv[3 + c] for c in range(1, p)])
+
+
 def kth_eig(pencil, k: int | None = None, m_max=20, tau_res=1e-10, tau_diff=1e-10,
-            tau_len=0.0, seed=0, max_iter=500, root_finder="bisection") -> Result:
+            tau_len=0.0, seed=0, max_iter=500, root_finder="bisection", si_block=0) -> Result:
     """Alg. 4 over the oracle's sparse LDL^T.  root_finder: "bisection" (Alg. 1')
-    or "interp" (stage2_interp) for stage 2."""
+    or "interp" (stage2_interp) for stage 2.  si_block: 1 the single-vector
+    Alg. 3; p > 1 the block method (stage3_block) with block size p; 0 (default)
+    Alg. 3 within 3 m + 30 steps, then the block method with p = m (a multiple
+    eigenvalue leaves Alg. 3 one Ritz value short, Section 3.4), and the block
+    method at once if stage 2 stopped on tau_len with more than m_max eigenvalues."""
     k = pencil.k if k is None else k
     P = osp.prepare(pencil)
     A, B = pencil.A(), pencil.B()
@@ -307,8 +469,24 @@ def kth_eig(pencil, k: int | None = None, m_max=20, tau_res=1e-10, tau_diff=1e-1
     else:
         raise ValueError(f"unknown root finder {root_finder!r}")
     nfac[0] += 1
-    lam, x, sj, sig, ib, ir, idf = stage3(P, k, sl, su, nl, nu_, A, B, v0s[1], tau_res,
-                                          tau_diff, max_iter)
+    m = nu_ - nl
+    F = osp.Factor(P, 0.5 * (sl + su))
+    block = si_block if si_block > 1 else 0
+    if si_block == 0 and m > m_max:
+        block = m
+    res = None
+    if block == 0:
+        try:
+            res = stage3(P, k, sl, su, nl, nu_, A, B, v0s[1], tau_res, tau_diff,
+                         max_iter if si_block == 1 else min(max_iter, 3 * m + 30), factor=F)
+        except NoConvergence:
+            if si_block == 1:
+                raise
+            block = m
+    if res is None:
+        res = stage3_block(P, k, sl, su, nl, nu_, A, B, block_start(pencil.n, block, seed),
+                           tau_res, tau_diff, max_iter, factor=F)
+    lam, x, sj, sig, ib, ir, idf = res
     x = x / np.sqrt(np.dot(x, B @ x))
     i = int(np.argmax(np.abs(x)))
     if x[i] < 0:
@@ -319,4 +497,4 @@ def kth_eig(pencil, k: int | None = None, m_max=20, tau_res=1e-10, tau_diff=1e-1
                   it_bound=ib, it_residual=ir, it_difference=idf,
                   sigmas=[a for a, _ in log], nus=[b for _, b in log],
                   rel_residual=float(np.linalg.norm(r) / np.linalg.norm(x)),
-                  n_factorizations=nfac[0])
+                  n_factorizations=nfac[0], si_block=max(block, 1))

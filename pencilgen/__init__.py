@@ -295,10 +295,34 @@ def chain(n=64, a=0.5, b=-1.0, k: int | None = None) -> Pencil:
                   k=(n // 2 if k is None else k), name=f"chain{n}")
 
 
+def doubled(pen: Pencil, seed: int | None = 0, k: int | None = None) -> Pencil:
+    """The direct sum of a pencil with itself, symmetrically permuted by a seeded
+    random permutation (seed None: the two copies kept in blocks): every
+    eigenvalue of ``pen`` becomes an exactly double one.  (A test input for
+    multiple eigenvalues; no arithmetic on the values.)"""
+    A = sp.block_diag([pen.A(), pen.A()], format="csr")
+    B = sp.block_diag([pen.B(), pen.B()], format="csr")
+    n = A.shape[0]
+    perm = np.arange(n) if seed is None else np.random.default_rng(seed).permutation(n)
+    A = A[perm][:, perm].tocsr()
+    B = B[perm][:, perm].tocsr()
+    A.sort_indices()
+    B.sort_indices()
+    P = (abs(A) + abs(B)).tocsr()
+    P.sort_indices()
+    out = Pencil(n=n, rowptr=P.indptr.astype(np.int64), col=P.indices.astype(np.int32),
+                 a_val=_on_pattern(A, P), b_val=_on_pattern(B, P),
+                 k=(n // 2 if k is None else k), name=f"doubled_{pen.name}")
+    out.perm = perm
+    return out
+
+
 def start_vectors(n: int, seed: int = 0, count: int = 4) -> np.ndarray:
     """Random starting vectors (N(0,1) entries), shape (count, n).  Row 0 starts
     the stage-1 Lanczos process, row 1 the shift-and-invert Lanczos process,
-    further rows serve restarts after a breakdown.  Drawn from a child of
+    rows 2 and 3 serve restarts after a breakdown, rows 4.. the further columns of
+    a block shift-and-invert start (column 0 is row 1).  The rows do not depend on
+    ``count`` (the normals are drawn row after row).  Drawn from a child of
     SeedSequence(seed) kept apart from the pencil's own stream."""
     child = np.random.SeedSequence(seed).spawn(2)[1]
     return np.random.default_rng(child).standard_normal(size=(count, n))

@@ -214,3 +214,48 @@ def test_three_stage_interp_matches_dense(which):
     for s, v in zip(ri.sigmas, ri.nus):
         assert v == od.nu(lam, s)
     assert ri.bisection_steps < rb.bisection_steps
+
+
+@pytest.fixture(scope="module")
+def doubled():
+    q = pg.doubled(pg.tb_cluster(200, seed=4), seed=None)
+    return q, od.eigvals(q)
+
+
+def test_block_si_lanczos_double_eigenvalues(doubled):
+    # every eigenvalue is exactly double: Alg. 3 with one start vector sees one
+    # copy of each, so it cannot validate m bounds; the block method does
+    q, lam = doubled
+    nA = od.norm_inf(q)
+    for k in (q.n // 2, q.n // 2 + 1, 241):
+        r = o3.kth_eig(q, k)
+        assert r.si_block > 1 and r.si_block == r.nu_upper - r.nu_lower
+        assert r.k_validated == k
+        assert abs(r.lam - lam[k - 1]) <= 1e-10 * nA
+        assert r.rel_residual <= 1e-9 * nA
+        assert abs(r.x @ (q.B() @ r.x) - 1.0) < 1e-12
+    with pytest.raises(o3.NoConvergence):
+        o3.kth_eig(q, q.n // 2, si_block=1, max_iter=120)
+
+
+def test_block_si_lanczos_matches_single_vector(tiny):
+    p, lam, X = tiny
+    k = p.n // 2
+    nA = od.norm_inf(p)
+    r1 = o3.kth_eig(p, k, si_block=1)
+    for b in (2, 5):
+        rb = o3.kth_eig(p, k, si_block=b)
+        assert rb.si_block == b and rb.k_validated == k
+        assert abs(rb.lam - lam[k - 1]) <= 1e-10 * nA
+        assert abs(rb.lam - r1.lam) <= 1e-12 * nA
+        assert rb.si_steps < r1.si_steps        # p vectors per step
+        x = od.sign_fix(X[:, k - 1])
+        assert np.linalg.norm(od.sign_fix(rb.x / np.sqrt(rb.x @ (p.B() @ rb.x))) - x) < 1e-8
+
+
+def test_block_start_columns():
+    n = 50
+    V = o3.block_start(n, 4)
+    sv = pg.start_vectors(n)
+    assert np.array_equal(V[:, 0], sv[1])
+    assert np.array_equal(V[:, 1], pg.start_vectors(n, count=7)[4])
