@@ -169,7 +169,10 @@ typedef struct {
   int32_t multisection;   /* shifts per stage-2 round (1: plain bisection)                    */
   uint64_t seed;          /* seed of the starting vectors, when start_vectors is NULL         */
   kth_precision si_precision;  /* precision of the shift-and-invert factor                   */
-  const double* start_vectors; /* optional host array [4][n]: row 0 stage 1, row 1 stage 3, rows 2.. restarts */
+  const double* start_vectors; /* optional host array [n_start_vectors][n]: row 0 stage 1, row 1
+                                  stage 3, rows 2-3 stage-1 restarts, rows 4.. further columns of a
+                                  block shift-and-invert start; rows not given are drawn by the
+                                  library's own generator                                      */
   const double* warm_interval; /* optional [2]: sigma_l, sigma_u (skip stages 1-2)             */
   const int64_t* warm_counts;  /* optional [2]: nu_l, nu_u matching warm_interval              */
   double ir_tol;          /* FP32 shift-and-invert solves: target backward error (0: 4 eps64) */
@@ -183,6 +186,14 @@ typedef struct {
                              at a fraction of the bracket within [1/64, 63/64]; after the
                              same end moved on two consecutive such steps the next shift
                              is the midpoint.  Same stopping rule.  Needs multisection = 1. */
+  int32_t si_block;       /* shift-and-invert Lanczos: 1 single vector (Alg. 3); p > 1 block
+                             method with block size p; 0 (automatic) Alg. 3 for at most
+                             3 m + 30 steps, then the block method with p = m (a multiple
+                             eigenvalue leaves Alg. 3 short of m Ritz values, Section 3.4),
+                             and the block method at once when stage 2 stopped on tau_len
+                             with more than m_max eigenvalues.  The block method validates
+                             overlapping bounds as a cluster (see kth_info.si_block).       */
+  int32_t n_start_vectors;  /* rows of start_vectors (0: 4)                                  */
 } kth_opts;
 
 typedef struct {
@@ -211,7 +222,8 @@ typedef struct {
                                  multiplier above 1e8 (restricted pivoting, Section 2.1)     */
   int32_t weak_pivot_kept;    /* counts accepted with a weak nonzero pivot after three moves   */
   int32_t stage1_restarts;    /* stage-1 Lanczos restarts after a breakdown (beta = 0)         */
-  int32_t pad0;
+  int32_t si_block;           /* block size of the shift-and-invert Lanczos that ran last (1:
+                                 Alg. 3); si_steps counts the steps of both methods         */
   int64_t m_max_used;         /* stage-2 stopping count in effect (opts.m_max, or the model's) */
 } kth_info;
 

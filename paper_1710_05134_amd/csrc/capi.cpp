@@ -71,6 +71,8 @@ void check_opts(const kth_opts& o) {
   if (!(o.ir_tol >= 0) || !std::isfinite(o.ir_tol)) throw Error(KTH_EINVAL, "ir_tol must be >= 0");
   if (o.batch_workers < 0 || o.batch_workers > 64) throw Error(KTH_EINVAL, "batch_workers must be in [0, 64]");
   if (o.root_finder != 0 && o.root_finder != 1) throw Error(KTH_EINVAL, "root_finder must be 0 or 1");
+  if (o.si_block < 0 || o.si_block > 64) throw Error(KTH_EINVAL, "si_block must be in [0, 64]");
+  if (o.n_start_vectors < 0) throw Error(KTH_EINVAL, "n_start_vectors must be >= 0");
   if (o.root_finder == 1 && o.multisection != 1)
     throw Error(KTH_EINVAL, "the interpolating root-finder takes one shift per step (multisection = 1)");
 }

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <atomic>
 #include <mutex>
 #include <numeric>
@@ -239,6 +240,393 @@ int64_t auto_m_max(int root_finder, double t_fact, double t_solve) {
   return std::min<int64_t>(20, std::max<int64_t>(2, (int64_t)std::lround(m)));
 }
 
+
+// Eigenvalues (ascending, w) and eigenvectors (columns of Z, column-major) of a
+// symmetric N x N matrix A (column-major, both triangles) by the cyclic Jacobi
+// method: rotations annihilate a(p, q) in turn until the off-diagonal part is
+// below 1e-16 of the Frobenius norm (at most 60 sweeps).
+void sym_eig_jacobi(int N, std::vector<double> A, std::vector<double>& w, std::vector<double>& Z) {
+  Z.assign((size_t)N * N, 0.0);
+  for (int i = 0; i < N; i++) Z[(size_t)i * N + i] = 1.0;
+  auto a = [&](int r, int c) -> double& { return A[(size_t)c * N + r]; };
+  double fro = 0;
+  for (double v : A) fro += v * v;
+  fro = std::sqrt(fro);
+  for (int sweep = 0; sweep < 60; sweep++) {
+    double off = 0;
+    for (int c = 0; c < N; c++)
+      for (int r = 0; r < c; r++) off += 2.0 * a(r, c) * a(r, c);
+    if (std::sqrt(off) <= 1e-16 * fro || fro == 0) break;
+    for (int p = 0; p < N - 1; p++)
+      for (int q = p + 1; q < N; q++) {
+        const double apq = a(p, q);
+        if (apq == 0.0) continue;
+        const double th = (a(q, q) - a(p, p)) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(1.0 + th * th));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
+        for (int r = 0; r < N; r++) {   // columns p, q
+          const double x = a(r, p), y = a(r, q);
+          a(r, p) = cs * x - sn * y;
+          a(r, q) = sn * x + cs * y;
+        }
+        for (int c = 0; c < N; c++) {   // rows p, q
+          const double x = a(p, c), y = a(q, c);
+          a(p, c) = cs * x - sn * y;
+          a(q, c) = sn * x + cs * y;
+        }
+        for (int r = 0; r < N; r++) {
+          const double x = Z[(size_t)p * N + r], y = Z[(size_t)q * N + r];
+          Z[(size_t)p * N + r] = cs * x - sn * y;
+          Z[(size_t)q * N + r] = sn * x + cs * y;
+        }
+      }
+  }
+  std::vector<int> ord(N);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
+  std::vector<double> Zs((size_t)N * N);
+  w.resize(N);
+  for (int i = 0; i < N; i++) {
+    w[i] = a(ord[i], ord[i]);
+    std::copy(Z.begin() + (size_t)ord[i] * N, Z.begin() + (size_t)(ord[i] + 1) * N, Zs.begin() + (size_t)i * N);
+  }
+  Z.swap(Zs);
+}
+
+// Largest singular value of the p x c matrix M (column-major).
+double norm2_mat(int p, int c, const std::vector<double>& M) {
+  std::vector<double> G((size_t)c * c, 0.0), w, Z;
+  for (int a = 0; a < c; a++)
+    for (int b = 0; b < c; b++) {
+      double t = 0;
+      for (int r = 0; r < p; r++) t += M[(size_t)a * p + r] * M[(size_t)b * p + r];
+      G[(size_t)b * c + a] = t;
+    }
+  sym_eig_jacobi(c, G, w, Z);
+  return std::sqrt(std::max(w.back(), 0.0));
+}
+
+// Upper-triangular Cholesky factor R (column-major, G = R^T R) of a symmetric
+// positive definite p x p matrix; false if a pivot is not positive.
+bool cholesky_upper(int p, const std::vector<double>& G, std::vector<double>& R) {
+  R.assign((size_t)p * p, 0.0);
+  for (int j = 0; j < p; j++) {
+    for (int i = 0; i <= j; i++) {
+      double t = G[(size_t)j * p + i];
+      for (int q = 0; q < i; q++) t -= R[(size_t)i * p + q] * R[(size_t)j * p + q];
+      if (i == j) {
+        if (!(t > 0)) return false;
+        R[(size_t)j * p + j] = std::sqrt(t);
+      } else {
+        R[(size_t)j * p + i] = t / R[(size_t)i * p + i];
+      }
+    }
+  }
+  return true;
+}
+
+// Inverse of an upper-triangular p x p matrix (column-major).
+std::vector<double> inv_upper(int p, const std::vector<double>& R) {
+  std::vector<double> X((size_t)p * p, 0.0);
+  for (int c = 0; c < p; c++) {
+    X[(size_t)c * p + c] = 1.0 / R[(size_t)c * p + c];
+    for (int r = c - 1; r >= 0; r--) {
+      double t = 0;
+      for (int q = r + 1; q <= c; q++) t += R[(size_t)q * p + r] * X[(size_t)c * p + q];
+      X[(size_t)c * p + r] = -t / R[(size_t)r * p + r];
+    }
+  }
+  return X;
+}
+
+// Result of the block shift-and-invert Lanczos.
+struct BlockOut {
+  kth_status st = KTH_ENOCONV;
+  double lam = 0, eta = 0;
+  int steps = 0, it_bound = 0, it_res = 0, it_diff = 0;
+  int xcol = -1;        // column of W.X holding the returned x_{l,2}
+};
+
+// Block shift-and-invert Lanczos for an interval that may hold multiple or
+// clustered eigenvalues (the modification Section 3.4 proposes; block size p).
+// With V = B^{-1} V~ kept B-orthonormal and V~ = B V, block by block:
+//   (A - sigma B)^{-1} B V_j = V_j T_j + V_{j+1} B_j E_j^T,
+// T_j block tridiagonal (diagonal blocks A_i from the first reorthogonalisation
+// pass, subdiagonal blocks B_i from the twice-repeated Cholesky B-orthonormalisation
+// of each new block).  A Ritz pair (theta, y) gives lambda = sigma + 1/theta and
+// x_2 = theta V_j y + V_{j+1} B_j E_j^T y, whose residual is -V~_{j+1} s with
+// s = B_j E_j^T y / theta, so the bound of Prop. 3 holds with ||s||_2 for |s|.
+// Validation: the m pairs of largest |theta|; all bounds inside [sigma_l,
+// sigma_u); overlapping bounds form a cluster C whose B-orthonormal Ritz block
+// has residual norm rho = ||B_j E_j^T Y_C||_2, so |C| eigenvalues lie within
+// rho / (|theta| (|theta| - rho)) of its lambdas (Kahan's theorem for the
+// operator (A - sigma B)^{-1} B, self-adjoint in the B inner product); single
+// bounds and cluster intervals must be pairwise disjoint.  Residual test per
+// pair; relative difference per single pair (as in Alg. 3), per cluster on its
+// eigenvalues (|lambda^(j) - lambda^(j-1)| <= tau_diff max(1, |lambda|)), with the
+// same cluster shape as the step before.  Bounds and cluster radii are not taken
+// below 64 eps (||A||_inf + |sigma| ||B||_inf), the rounding level of the solves.
+BlockOut si_block_run(Pencil& P, NumFactor& FS, Work& W, int64_t k, double sl, double su,
+                      int64_t nl, int64_t nu_, double sigma, int p, const kth_opts& o,
+                      const std::function<void(int, std::vector<double>&)>& start_vec,
+                      const std::function<void()>& refactor_fp64) {
+  Ctx* c = P.ctx;
+  hipStream_t st = c->stream;
+  const int64_t n = P.n;
+  const int64_t l = k - nl;
+  const int m = (int)(nu_ - nl);
+  const double floor_b = 64.0 * 2.220446049250313e-16 * (P.normA_inf + std::fabs(sigma) * P.normB_inf);
+  BlockOut out;
+  DBuf<double> zero, zcu, Cb;
+  zero.alloc(c, n);
+  KTH_HIP(hipMemsetAsync(zero.get(), 0, sizeof(double) * n, st));
+  zcu.alloc(c, 4096);
+  KTH_HIP(hipMemsetAsync(zcu.get(), 0, sizeof(double) * 4096, st));
+  W.ensure_m(std::max(m, p), 1);
+  // X := X * C for a block of q columns at column c0 of V or Vt (through W.X)
+  auto times_small = [&](double* base, int q, const std::vector<double>& C) {
+    Cb.alloc(c, C.size());
+    h2d(c, Cb.get(), C.data(), C.size());
+    ritz_vectors(n, q, q, base, n, Cb.get(), zero.get(), zcu.get(), W.X.get(), n, st);
+    KTH_HIP(hipMemcpyAsync(base, W.X.get(), sizeof(double) * n * q, hipMemcpyDeviceToDevice, st));
+    c->sync();   // Cb is released on the next call
+  };
+  // Gram matrix X^T Y of two blocks of q columns
+  auto gram = [&](const double* X, const double* Y, int q) {
+    std::vector<double> G((size_t)q * q);
+    for (int b = 0; b < q; b++) {
+      multidot(n, q, X, n, Y + (size_t)b * n, W.partial.get(), W.h.get(), 1.0, st);
+      d2h(c, G.data() + (size_t)b * q, W.h.get(), q);
+    }
+    return G;
+  };
+  // B-orthonormalise the block at column c0 (twice); R: the total factor
+  auto borth = [&](int c0, std::vector<double>& R) -> bool {
+    R.assign((size_t)p * p, 0.0);
+    for (int i = 0; i < p; i++) R[(size_t)i * p + i] = 1.0;
+    for (int pass = 0; pass < 2; pass++) {
+      std::vector<double> G = gram(W.v(c0), W.vt(c0), p), Rc;
+      for (int a = 0; a < p; a++)
+        for (int b = 0; b < a; b++) {
+          const double t = 0.5 * (G[(size_t)a * p + b] + G[(size_t)b * p + a]);
+          G[(size_t)a * p + b] = G[(size_t)b * p + a] = t;
+        }
+      if (!cholesky_upper(p, G, Rc)) return false;
+      const std::vector<double> Ri = inv_upper(p, Rc);
+      times_small(W.v(c0), p, Ri);
+      times_small(W.vt(c0), p, Ri);
+      std::vector<double> Rn((size_t)p * p, 0.0);   // Rc * R
+      for (int a = 0; a < p; a++)
+        for (int b = 0; b < p; b++) {
+          double t = 0;
+          for (int q = 0; q < p; q++) t += Rc[(size_t)q * p + a] * R[(size_t)b * p + q];
+          Rn[(size_t)b * p + a] = t;
+        }
+      R.swap(Rn);
+    }
+    return true;
+  };
+  W.ensure_cols(2 * p);
+  std::vector<double> hv;
+  for (int q = 0; q < p; q++) {
+    start_vec(q == 0 ? 1 : 3 + q, hv);
+    h2d(c, W.v(q), hv.data(), n);
+    spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.v(q), nullptr, W.vt(q), st);
+  }
+  std::vector<double> R0;
+  if (!borth(0, R0)) throw Error(KTH_ENOCONV, "block Lanczos: the start block is rank deficient");
+  std::vector<std::vector<double>> Ab, Bb;
+  std::vector<int> prev_shape;
+  std::vector<double> prev_la;
+  bool have_prev = false;
+  for (int j = 1; j <= o.max_lanczos; j++) {
+    const int base = (j - 1) * p, nxt = j * p;
+    W.ensure_cols(nxt + p);
+    for (int q = 0; q < p; q++) {
+      SolveOutcome so = solve_refined(P, FS, W.vt(base + q), W.v(nxt + q), o.ir_tol > 0 ? o.ir_tol : kIrTol);
+      if (!so.converged) {
+        refactor_fp64();
+        solve_enqueue_f(P, FS, W.vt(base + q), W.v(nxt + q));
+      }
+      spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.v(nxt + q), nullptr,
+            W.vt(nxt + q), st);
+    }
+    std::vector<double> Aj((size_t)p * p);
+    for (int q = 0; q < p; q++) {
+      double* w = W.v(nxt + q);
+      double* bw = W.vt(nxt + q);
+      multidot(n, nxt, W.Vt.get(), n, w, W.partial.get(), W.h.get(), 1.0, st);
+      d2h(c, Aj.data() + (size_t)q * p, W.h.get() + base, p);
+      multiaxpy(n, nxt, W.V.get(), n, W.h.get(), w, W.Vt.get(), bw, st);
+      multidot(n, nxt, W.Vt.get(), n, w, W.partial.get(), W.h2.get(), 1.0, st);
+      multiaxpy(n, nxt, W.V.get(), n, W.h2.get(), w, W.Vt.get(), bw, st);
+    }
+    for (int a = 0; a < p; a++)
+      for (int b = 0; b < a; b++) {
+        const double t = 0.5 * (Aj[(size_t)a * p + b] + Aj[(size_t)b * p + a]);
+        Aj[(size_t)a * p + b] = Aj[(size_t)b * p + a] = t;
+      }
+    Ab.push_back(Aj);
+    std::vector<double> Rj;
+    if (!borth(nxt, Rj)) throw Error(KTH_ENOCONV, "block Lanczos: a new block is rank deficient");
+    out.steps = j;
+    if ((int64_t)j * p >= m) {
+      const int N = j * p;
+      std::vector<double> T((size_t)N * N, 0.0);
+      for (int i = 0; i < j; i++)
+        for (int a = 0; a < p; a++)
+          for (int b = 0; b < p; b++) {
+            T[(size_t)(i * p + b) * N + i * p + a] = Ab[i][(size_t)b * p + a];
+            if (i + 1 < j) {
+              const double v = Bb[i][(size_t)b * p + a];   // rows (i+1) p + a, columns i p + b
+              T[(size_t)(i * p + b) * N + (i + 1) * p + a] = v;
+              T[(size_t)((i + 1) * p + a) * N + i * p + b] = v;
+            }
+          }
+      std::vector<double> th, Y;
+      sym_eig_jacobi(N, T, th, Y);
+      std::vector<int> ord(N);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        if (std::fabs(th[a]) != std::fabs(th[b])) return std::fabs(th[a]) > std::fabs(th[b]);
+        return th[a] > th[b];
+      });
+      ord.resize(m);
+      std::vector<double> lam(m), eta(m), S((size_t)p * m), RY((size_t)p * m);
+      for (int q = 0; q < m; q++) {
+        const int i = ord[q];
+        const double ts = th[i];
+        lam[q] = sigma + 1.0 / ts;
+        double sn = 0;
+        for (int a = 0; a < p; a++) {   // (B_j E_j^T y)_a
+          double t = 0;
+          for (int b = a; b < p; b++) t += Rj[(size_t)b * p + a] * Y[(size_t)i * N + (N - p) + b];
+          RY[(size_t)q * p + a] = t;
+          S[(size_t)q * p + a] = t / ts;
+          sn += (t / ts) * (t / ts);
+        }
+        sn = std::sqrt(sn);
+        eta[q] = std::max((1.0 / std::fabs(ts)) * sn / std::sqrt(1.0 + sn * sn), floor_b);
+      }
+      bool incl = true;
+      for (int q = 0; q < m; q++) incl = incl && (lam[q] - eta[q] >= sl) && (lam[q] + eta[q] < su);
+      std::vector<int> asc(m);
+      std::iota(asc.begin(), asc.end(), 0);
+      std::stable_sort(asc.begin(), asc.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+      std::vector<std::vector<int>> comps{{asc[0]}};
+      for (int q = 1; q < m; q++) {
+        const int a = asc[q - 1], b = asc[q];
+        if (lam[a] + eta[a] >= lam[b] - eta[b]) comps.back().push_back(b);
+        else comps.push_back({b});
+      }
+      bool ok = incl;
+      std::vector<std::pair<double, double>> iv;
+      for (const auto& C : comps) {
+        if (C.size() == 1) {
+          iv.push_back({lam[C[0]] - eta[C[0]], lam[C[0]] + eta[C[0]]});
+          continue;
+        }
+        std::vector<double> M((size_t)p * C.size());
+        double tmin = INFINITY;
+        for (size_t q = 0; q < C.size(); q++) {
+          std::copy(RY.begin() + (size_t)C[q] * p, RY.begin() + (size_t)(C[q] + 1) * p,
+                    M.begin() + q * p);
+          tmin = std::min(tmin, std::fabs(th[ord[C[q]]]));
+        }
+        const double rho = norm2_mat(p, (int)C.size(), M);
+        if (!(rho < tmin)) { ok = false; break; }
+        double lo = INFINITY, hi = -INFINITY;
+        for (int q : C) {
+          const double tc = std::fabs(th[ord[q]]);
+          const double e = std::max(rho / (tc * (tc - rho)), floor_b);
+          lo = std::min(lo, lam[q] - e);
+          hi = std::max(hi, lam[q] + e);
+        }
+        iv.push_back({lo, hi});
+      }
+      if (ok)
+        for (size_t q = 0; q < iv.size(); q++)
+          ok = ok && iv[q].first >= sl && iv[q].second < su && (q == 0 || iv[q - 1].second < iv[q].first);
+      // Ritz vectors x_2 = [V_j, V_{j+1}] [theta y; B_j E_j^T y], in column groups
+      const int J = N + p;
+      const int mg = std::max(1, std::min(m, 8000 / (J + 1)));
+      for (int g0 = 0; g0 < m; g0 += mg) {
+        const int cnt = std::min(mg, m - g0);
+        std::vector<double> C((size_t)J * cnt);
+        for (int q = 0; q < cnt; q++) {
+          const int i = ord[g0 + q];
+          for (int r = 0; r < N; r++) C[(size_t)q * J + r] = th[i] * Y[(size_t)i * N + r];
+          for (int a = 0; a < p; a++) C[(size_t)q * J + N + a] = RY[(size_t)(g0 + q) * p + a];
+        }
+        Cb.alloc(c, C.size());
+        h2d(c, Cb.get(), C.data(), C.size());
+        ritz_vectors(n, J, cnt, W.V.get(), n, Cb.get(), zero.get(), zcu.get(), W.X.get() + (size_t)g0 * n, n, st);
+        c->sync();
+      }
+      std::vector<double> xn2(m);
+      multidot2(n, m, W.X.get(), n, W.X.get(), n, W.partial.get(), W.sc.get(), 1.0, st);
+      d2h(c, xn2.data(), W.sc.get(), m);
+      const std::vector<double> Gt = gram(W.vt(nxt), W.vt(nxt), p);
+      bool res_ok = true;
+      for (int q = 0; q < m; q++) {
+        double rr = 0;
+        for (int a = 0; a < p; a++)
+          for (int b = 0; b < p; b++) rr += S[(size_t)q * p + a] * Gt[(size_t)b * p + a] * S[(size_t)q * p + b];
+        res_ok = res_ok && (std::sqrt(std::max(rr, 0.0)) / std::sqrt(xn2[q]) < o.tau_res);
+      }
+      std::vector<int> shape;
+      for (const auto& C : comps) shape.push_back((int)C.size());
+      std::vector<double> la(m);
+      std::vector<int32_t> pa(m);
+      std::vector<double> fa(m);
+      for (int q = 0; q < m; q++) {
+        la[q] = lam[asc[q]];
+        pa[q] = asc[q];
+        fa[q] = 1.0 / std::sqrt(xn2[asc[q]]);
+      }
+      h2d(c, W.perm_d.get(), pa.data(), m);
+      h2d(c, W.f_d.get(), fa.data(), m);
+      gather_cols(n, m, W.X.get(), n, W.perm_d.get(), W.f_d.get(), W.Xn.get(), n, st);
+      bool diff_ok = false;
+      if (have_prev && shape == prev_shape) {
+        std::vector<double> dd(m), sg(m);
+        multidot2(n, m, W.Xn.get(), n, W.Prev.get(), n, W.partial.get(), W.sc.get(), 1.0, st);
+        d2h(c, dd.data(), W.sc.get(), m);
+        for (int q = 0; q < m; q++) sg[q] = dd[q] < 0 ? -1.0 : 1.0;
+        h2d(c, W.f_d.get(), sg.data(), m);
+        diff_cols(n, m, W.Xn.get(), n, W.f_d.get(), W.Prev.get(), n, W.Dif.get(), n, st);
+        multidot2(n, m, W.Dif.get(), n, W.Dif.get(), n, W.partial.get(), W.sc.get(), 1.0, st);
+        d2h(c, dd.data(), W.sc.get(), m);
+        diff_ok = true;
+        int pos = 0;
+        for (int sz : shape) {
+          for (int q = pos; q < pos + sz; q++)
+            diff_ok = diff_ok && (sz == 1 ? std::sqrt(dd[q]) < o.tau_diff
+                                          : std::fabs(la[q] - prev_la[q]) <= o.tau_diff * std::max(1.0, std::fabs(la[q])));
+          pos += sz;
+        }
+      }
+      W.Xn.swap(W.Prev);
+      have_prev = true;
+      prev_shape = shape;
+      prev_la = la;
+      if (ok && !out.it_bound) out.it_bound = j;
+      if (res_ok && !out.it_res) out.it_res = j;
+      if (diff_ok && !out.it_diff) out.it_diff = j;
+      if (ok && res_ok && diff_ok) {
+        const int q = asc[l - 1];
+        out.st = KTH_OK;
+        out.lam = lam[q];
+        out.eta = eta[q];
+        out.xcol = q;
+        return out;
+      }
+    }
+    Bb.push_back(Rj);
+  }
+  return out;
+}
+
 }  // namespace
 
 void numeric_factor(Pencil& P, NumFactor& F, double sigma, kth_precision prec) {
@@ -439,8 +827,9 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   Shifts log;
   int64_t nfac = 0;
   double t_task[7] = {P.S.t_order + P.S.t_symbolic, 0, 0, 0, 0, 0, 0};
-  auto start_vec = [&](int row, std::vector<double>& v) {
-    if (o.start_vectors) v.assign(o.start_vectors + (size_t)row * n, o.start_vectors + (size_t)(row + 1) * n);
+  const int n_sv = o.start_vectors ? (o.n_start_vectors > 0 ? o.n_start_vectors : 4) : 0;
+  std::function<void(int, std::vector<double>&)> start_vec = [&](int row, std::vector<double>& v) {
+    if (row < n_sv) v.assign(o.start_vectors + (size_t)row * n, o.start_vectors + (size_t)(row + 1) * n);
     else gen_start(n, o.seed, row, v);
   };
   std::vector<double> hv;
@@ -650,7 +1039,31 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   bool ever_incl_not_disj = false;
   kth_status result = KTH_ENOCONV;
   double lam_out = 0, eta_out = 0;
-  for (int j = 1; j <= o.max_lanczos; j++) {
+  // x = x_{l,2}, B-normalised, largest-|.| entry positive; explicit residual
+  auto finish = [&](double* xq) {
+    spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), xq, W.ya.get(), W.yb.get(), st);
+    double xbx = dot_dev(W, xq, W.yb.get());
+    double xx = dot_dev(W, xq, xq);
+    residual(n, lam_out, W.ya.get(), W.yb.get(), W.w.get(), st);
+    double rr = dot_dev(W, W.w.get(), W.w.get());
+    const double scale = 1.0 / std::sqrt(xbx);
+    std::vector<double> hx(n);
+    d2h(c, hx.data(), xq, n);
+    int64_t imax = 0;
+    for (int64_t i = 1; i < n; i++) if (std::fabs(hx[i]) > std::fabs(hx[imax])) imax = i;
+    const double sgn = hx[imax] < 0 ? -1.0 : 1.0;
+    if (xout) for (int64_t i = 0; i < n; i++) xout[i] = sgn * scale * hx[i];
+    info->rel_residual = std::sqrt(rr) / std::sqrt(xx);
+    info->rel_residual_normA = info->rel_residual / (nA > 0 ? nA : 1.0);
+  };
+  // block size: si_block > 1 as given; 0 (automatic) the block method with p = m
+  // when stage 2 stopped with more than m_max eigenvalues (a cluster), else
+  // Alg. 3 for at most 3 m + 30 steps and the block method after that
+  const int64_t mcap = m_eff > 0 ? m_eff : 20;
+  int block_p = o.si_block > 1 ? o.si_block : 0;
+  if (o.si_block == 0 && m > mcap) block_p = m;
+  const int single_cap = o.si_block == 1 ? o.max_lanczos : std::min(o.max_lanczos, 3 * m + 30);
+  for (int j = 1; j <= (block_p ? 0 : single_cap); j++) {
     W.ensure_cols(j + 1);
     // w = (A - sigma B)^{-1} v~_j, Bw = B w
     {
@@ -762,28 +1175,39 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
         const int q = asc[l - 1];
         lam_out = lam[q];
         eta_out = eta[q];
-        // x = x_{l,2}, B-normalised, largest-|.| entry positive
-        double* xq = W.X.get() + (size_t)n * q;
-        spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), xq, W.ya.get(), W.yb.get(), st);
-        double xbx = dot_dev(W, xq, W.yb.get());
-        double xx = dot_dev(W, xq, xq);
-        residual(n, lam_out, W.ya.get(), W.yb.get(), W.w.get(), st);
-        double rr = dot_dev(W, W.w.get(), W.w.get());
-        const double scale = 1.0 / std::sqrt(xbx);
-        std::vector<double> hx(n);
-        d2h(c, hx.data(), xq, n);
-        int64_t imax = 0;
-        for (int64_t i = 1; i < n; i++) if (std::fabs(hx[i]) > std::fabs(hx[imax])) imax = i;
-        const double sgn = hx[imax] < 0 ? -1.0 : 1.0;
-        if (xout) for (int64_t i = 0; i < n; i++) xout[i] = sgn * scale * hx[i];
-        info->rel_residual = std::sqrt(rr) / std::sqrt(xx);
-        info->rel_residual_normA = info->rel_residual / (nA > 0 ? nA : 1.0);
+        finish(W.X.get() + (size_t)n * q);
         result = KTH_OK;
         break;
       }
     }
     if (beta == 0) break;
     be.push_back(beta);
+  }
+  if (result != KTH_OK && o.si_block == 0 && block_p == 0) block_p = m;
+  int block_steps = 0;
+  if (result != KTH_OK && block_p > 0) {
+    auto refactor64 = [&]() {
+      const double ts = now_s();
+      const double sig_keep = sigma;
+      si_factor(KTH_FP64);
+      if (sigma != sig_keep)
+        throw Error(KTH_ESINGULAR, "FP64 fallback factor hit a zero pivot at the FP32 shift");
+      t_task[5] += now_s() - ts;
+      ir_fallback = 1;
+    };
+    BlockOut bo = si_block_run(P, FS, W, k, sl, su, nl, nu_, sigma, block_p, o, start_vec, refactor64);
+    block_steps = bo.steps;
+    it_bound = bo.it_bound;
+    it_res = bo.it_res;
+    it_diff = bo.it_diff;
+    if (bo.st == KTH_OK) {
+      lam_out = bo.lam;
+      eta_out = bo.eta;
+      finish(W.X.get() + (size_t)n * bo.xcol);
+      result = KTH_OK;
+    } else {
+      ever_incl_not_disj = true;   // the interval's eigenvalues were not resolved
+    }
   }
   t_task[6] = now_s() - t3;
   if (result != KTH_OK && ever_incl_not_disj) result = KTH_ECLUSTER;
@@ -796,7 +1220,8 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   info->sigma_si = sigma;
   info->stage1_steps = s1;
   info->bisection_steps = s2;
-  info->si_steps = j_done;
+  info->si_steps = j_done + block_steps;
+  info->si_block = block_p > 0 ? block_p : 1;
   info->it_bound = it_bound;
   info->it_residual = it_res;
   info->it_difference = it_diff;

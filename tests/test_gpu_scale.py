@@ -92,3 +92,23 @@ def test_fem_large_closed_form(K, ctx):
         if ref[q] - ref[q - 1] < 1e-9 * ref[-1]:
             continue
         assert P.nu(s) == q
+
+
+def test_eig_n131k_interp(K, ctx):
+    """The interpolating stage 2 at n = 131072 against the oracle's own run of it."""
+    gold = _golden("three_stage_n131k_interp.json")
+    assert gold, "no stored oracle run of the interpolating stage 2 for n131k"
+    g = gold[0]
+    p = pg.workload("n131k")
+    note("kth_eig n131k root_finder=1")
+    P = K.Pencil.from_pencilgen(ctx, p)
+    lam, x, info = P.eig(p.k, start_vectors=pg.start_vectors(p.n), root_finder=1, m_max=g.get("m_max", 20))
+    nA = float(np.add.reduceat(np.abs(p.a_val), p.rowptr[:-1]).max())
+    assert info["k_validated"] == p.k
+    assert abs(lam - g["lam"]) <= 1e-10 * nA
+    assert np.linalg.norm(p.A() @ x - lam * (p.B() @ x)) / (nA * np.linalg.norm(x)) <= 1e-9
+    # the same shifts (same stage-1 Ritz values, same interpolation arithmetic) and counts
+    assert info["sigmas"] == g["sigmas"] and info["nus"] == g["nus"]
+    assert (info["sigma_lower"], info["sigma_upper"], info["nu_lower"], info["nu_upper"]) == \
+        (g["sigma_lower"], g["sigma_upper"], g["nu_lower"], g["nu_upper"])
+    assert info["bisection_steps"] == g["bisection_steps"]
