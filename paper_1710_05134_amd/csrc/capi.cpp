@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -148,6 +149,8 @@ kth_status kth_ctx_create(int device, void* hip_stream, kth_alloc_fn alloc, kth_
     c->c.afn = alloc;
     c->c.ffn = free_fn;
     c->c.user = user;
+    const char* g = std::getenv("KTH_GRAPHS");
+    c->c.use_graphs = !(g && g[0] == '0');
   });
   if (st == KTH_OK) *out = c.release();
   return st;

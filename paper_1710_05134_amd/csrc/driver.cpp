@@ -836,7 +836,10 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
 
   // ---- task (ii): factor of B (its inertia must be (0, 0, n)) ----
   double t0 = now_s();
-  NumFactor FB;
+  // the factor of B and the shift-and-invert factor are kept by the pencil, so
+  // later calls replay their captured launch sequences
+  if (!P.fb) { P.fb.reset(new NumFactor()); P.fb->replay = true; }
+  NumFactor& FB = *P.fb;
   factor_alloc(P, FB);
   factor_enqueue(P, FB, 0.0, true);
   factor_read_stats(P, FB);
@@ -989,7 +992,8 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   const int m = (int)(nu_ - nl);
   double sigma = 0.5 * (sl + su);
   double tsi = now_s();
-  NumFactor FS;
+  if (!P.fs) { P.fs.reset(new NumFactor()); P.fs->replay = true; }
+  NumFactor& FS = *P.fs;
   // the shift-and-invert factor: FP64, or FP32 with FP64 refinement of every solve
   // (falls back to FP64 at the same shift if a refinement stalls)
   auto si_factor = [&](kth_precision prec) {

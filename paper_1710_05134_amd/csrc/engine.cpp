@@ -84,6 +84,7 @@ void Ctx::ensure_workers(int nw) {
     w->afn = afn;
     w->ffn = ffn;
     w->user = user;
+    w->use_graphs = use_graphs;
     KTH_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
     w->own_stream = true;
     workers.push_back(std::move(w));
@@ -396,6 +397,7 @@ void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* arp, const int32
   P.meta.imap = P.d_imap.get();
   P.ws_batches = 0;
   P.scratch.reset(new NumFactor());
+  P.scratch->replay = true;
   factor_alloc(P, *P.scratch);
   ctx->sync();
 }
@@ -453,6 +455,10 @@ static void ensure_workspace(Pencil& P, int nb) {
 void factor_alloc(Pencil& P, NumFactor& F, int nb, kth_precision prec) {
   Ctx* c = P.ctx;
   if (nb < 1 || nb > kMaxBatch) throw Error(KTH_EINVAL, "batch of factorizations out of range");
+  if (F.p == &P && F.nb == nb && F.prec == prec && F.L.p) {   // already laid out
+    ensure_workspace(P, nb);
+    return;
+  }
   F.p = &P;
   F.nb = nb;
   F.prec = prec;
@@ -515,11 +521,14 @@ void factor_enqueue(Pencil& P, NumFactor& F, double sigma, bool mode_b, FactorPr
 }
 
 template <typename T>
+static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const double* bv,
+                        FactorProfile* prof);
+
+template <typename T>
 static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int nb, bool mode_b,
                              FactorProfile* prof) {
   Ctx* c = P.ctx;
   hipStream_t st = c->stream;
-  const Symbolic& S = P.S;
   if (nb < 1 || nb > F.nb) throw Error(KTH_EINVAL, "batch larger than the factor storage");
   ensure_workspace(P, nb);
   F.sigma = sigmas[0];
@@ -529,6 +538,53 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
   const double* av = mode_b ? P.zeros.get() : P.aval.get();
   const double* bv = P.bval.get();
   launch_set_scalars(F.sig.get(), nb, sv, st);
+  c->ensure_aux();
+  // the rest of the sequence depends on the shifts only through F.sig: for a factor
+  // that is used again and again (the pencil's inertia-only factor), captured once
+  // into a graph and replayed (not when every launch is timed)
+  const bool graph = c->use_graphs && F.replay && !prof;
+  const void* key[kGraphKey] = {F.L.get(), P.U.get(), P.W.get(), P.Tinv.get(), P.Part.get(),
+                                F.stats.get(), F.sig.get(), av, bv, F.D.get(), F.E.get(), F.tperm.get()};
+  FactorGraph& fg = F.graphs[mode_b ? 1 : 0];
+  if (graph && fg.exec && fg.nb == nb && std::equal(key, key + kGraphKey, fg.key)) {
+    KTH_HIP(hipGraphLaunch(fg.exec, st));
+    return;
+  }
+  if (graph) {
+    if (fg.exec) {
+      KTH_HIP(hipGraphExecDestroy(fg.exec));
+      fg.exec = nullptr;
+    }
+    KTH_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  }
+  try {
+    factor_body<T>(P, F, nb, av, bv, prof);
+  } catch (...) {
+    if (graph) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(st, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    throw;
+  }
+  if (graph) {
+    hipGraph_t g = nullptr;
+    KTH_HIP(hipStreamEndCapture(st, &g));
+    const hipError_t ie = hipGraphInstantiate(&fg.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    KTH_HIP(ie);
+    std::copy(key, key + kGraphKey, fg.key);
+    fg.nb = nb;
+    KTH_HIP(hipGraphLaunch(fg.exec, st));
+  }
+}
+
+template <typename T>
+static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const double* bv,
+                        FactorProfile* prof) {
+  Ctx* c = P.ctx;
+  hipStream_t st = c->stream;
+  const Symbolic& S = P.S;
   launch_fill_stats(F.stats.get(), nb, st);
   Batch bt;
   bt.sL = P.S.lptr[P.S.nsup];
@@ -539,7 +595,6 @@ static void factor_enqueue_t(Pencil& P, NumFactor& F, const double* sigmas, int 
   bt.sN = P.n;
   bt.sig = F.sig.get();
   const int32_t* sched = P.d_sched.get();
-  c->ensure_aux();
   T* Lf = reinterpret_cast<T*>(F.L.get());
   T* Uf = reinterpret_cast<T*>(P.U.get());
   T* Wf = reinterpret_cast<T*>(P.W.get());

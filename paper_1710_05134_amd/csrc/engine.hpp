@@ -40,6 +40,9 @@ struct Ctx {
   void* user = nullptr;
   std::string last_error;
   double cur_bytes = 0, peak_bytes = 0;
+  // factorizations replay a captured HIP graph of their launch sequence
+  // (environment KTH_GRAPHS=0 at context creation: launch kernel by kernel)
+  bool use_graphs = true;
   // second stream for the pivot tile of the next step (look-ahead), and the two
   // events that order it against the context stream
   hipStream_t aux = nullptr;
@@ -149,10 +152,29 @@ struct Pencil {
   DBuf<double> Part;   // partial products of split column-block updates (ws_batches copies)
   std::unique_ptr<NumFactor> scratch;   // factor reused by inertia-only calls
   std::unique_ptr<NumFactor> batchF;    // batched inertia-only factorizations (multisection)
+  std::unique_ptr<NumFactor> fb, fs;    // kth_eig's factor of B and shift-and-invert factor
   double flops() const { return S.flops; }
 };
 
+// Instantiated graph of one factorization's launch sequence (everything after the
+// shifts are written to the device), valid for the buffers it was captured with.
+constexpr int kGraphKey = 12;
+struct FactorGraph {
+  hipGraphExec_t exec = nullptr;
+  const void* key[kGraphKey] = {};
+  int nb = 0;
+};
+
 struct NumFactor {
+  NumFactor() = default;
+  NumFactor(const NumFactor&) = delete;
+  NumFactor& operator=(const NumFactor&) = delete;
+  ~NumFactor() {
+    for (FactorGraph& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  }
+  FactorGraph graphs[2];      // [factor of B itself]
+  bool replay = false;        // factorizations go through a captured graph
   Pencil* p = nullptr;
   int nb = 1;                 // batched factorizations held (solves use batch 0)
   double sigma = 0;
