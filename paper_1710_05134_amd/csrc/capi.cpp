@@ -395,7 +395,8 @@ kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int
   if (!ctx || np < 0 || (np > 0 && (!p || !k || !lambda || !per_pencil))) return KTH_EINVAL;
   kth_opts o;
   if (opts) o = *opts; else kth_opts_default(&o);
-  return guarded(&ctx->c, [&] {
+  std::string batch_msg;
+  kth_status st = guarded(&ctx->c, [&] {
     check_opts(o);
     set_device(ctx->c);
     std::vector<Pencil*> ps(np);
@@ -408,8 +409,12 @@ kth_status kth_eig_batch(kth_ctx ctx, int32_t np, const kth_pencil* p, const int
     std::sort(sorted.begin(), sorted.end());
     if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
       throw Error(KTH_EINVAL, "the same pencil appears more than once in the batch");
+    ctx->c.last_error.clear();
     eig_batch(ctx->c, ps, k, o, lambda, x, info, per_pencil);
+    batch_msg = ctx->c.last_error;
   });
+  if (st == KTH_OK) ctx->c.last_error = batch_msg;   // a failing pencil's message, if any
+  return st;
 }
 
 kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double g,

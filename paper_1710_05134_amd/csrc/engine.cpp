@@ -84,7 +84,9 @@ void Ctx::ensure_workers(int nw) {
     w->afn = afn;
     w->ffn = ffn;
     w->user = user;
-    w->use_graphs = use_graphs;
+    // worker threads launch kernel by kernel: graphs replayed from several threads at
+    // once gave inertia counts read before all of a replay's kernels had finished
+    w->use_graphs = false;
     KTH_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
     w->own_stream = true;
     workers.push_back(std::move(w));

@@ -184,8 +184,9 @@ def test_option_validation(K, ctx):
     p = pg.tb_supercell((2, 2, 2), seed=6)
     note("option validation")
     P = K.Pencil.from_pencilgen(ctx, p)
-    for bad in (dict(multisection=0), dict(multisection=65), dict(m_max=0), dict(ir_tol=-1.0),
-                dict(si_precision=7), dict(max_lanczos=0), dict(tau_res=0.0)):
+    for bad in (dict(multisection=0), dict(multisection=65), dict(m_max=-1), dict(ir_tol=-1.0),
+                dict(si_precision=7), dict(max_lanczos=0), dict(tau_res=0.0), dict(root_finder=2),
+                dict(root_finder=1, multisection=3), dict(si_block=65), dict(si_block=-1)):
         with pytest.raises(K.KthError) as e:
             P.eig(p.n // 2, **bad)
         assert e.value.status == K.KTH_EINVAL, bad

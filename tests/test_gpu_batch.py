@@ -3,8 +3,8 @@
 * 64 shifts of the n = 131072 pencil factored together: every count equals the
   one-at-a-time count and, at the oracle's stored shifts, the oracle's count;
 * multisection inside kth_eig gives the same validated eigenpair;
-* a batch of uneven open-cluster pencils through kth_eig_batch against the
-  dense oracle.
+* all 256 uneven open-cluster pencils through kth_eig_batch against the
+  dense oracle's stored values.
 """
 import glob
 import json
@@ -67,18 +67,28 @@ def test_multisection_eig(K, ctx):
         assert info["bisection_steps"] < base[2]["bisection_steps"]
 
 
-def test_eig_batch_uneven_pencils(K, ctx):
+def test_eig_batch_256_uneven_pencils(K, ctx):
+    """All 256 pencils of the uneven batch (n in [500, 8000]) in one kth_eig_batch
+    call, each against the dense oracle's lambda_k stored in
+    tests/golden/batch_dense_256.json (written by make_golden.py from oracle.dense)."""
+    gold = json.load(open(os.path.join(GOLD, "batch_dense_256.json")))["pencils"]
     pens = pg.uneven_batch(count=256, seed=0)
-    pick = [q for q in range(len(pens)) if pens[q].n <= 2400][:6]
-    sel = [pens[q] for q in pick]
-    note(f"eig batch {[p.n for p in sel]}")
-    Ps = [K.Pencil.from_pencilgen(ctx, p) for p in sel]
-    res = K.eig_batch(ctx, Ps, [p.k for p in sel])
-    for p, (st, lam, x, info) in zip(sel, res):
-        assert st == K.KTH_OK
-        lam_ref, _ = od.kth(p, p.k)
+    assert len(gold) == len(pens)
+    note(f"eig batch of {len(pens)} pencils, n {min(p.n for p in pens)}..{max(p.n for p in pens)}")
+    Ps = [K.Pencil.from_pencilgen(ctx, p) for p in pens]
+    t0 = time.perf_counter()
+    res = K.eig_batch(ctx, Ps, [p.k for p in pens])
+    print(f"256 pencils: {time.perf_counter() - t0:.2f} s")
+    for p, g, (st, lam, x, info) in zip(pens, gold, res):
+        assert (g["n"], g["k"]) == (p.n, p.k)
+        assert st == K.KTH_OK, (g["i"], st)
         assert info["k_validated"] == p.k
-        assert abs(lam - lam_ref) <= 1e-10 * od.norm_inf(p)
+        assert abs(lam - g["lam"]) <= 1e-10 * g["norm_a_inf"], (g["i"], lam, g["lam"])
+        r = p.A() @ x - lam * (p.B() @ x)
+        assert np.linalg.norm(r) / (g["norm_a_inf"] * np.linalg.norm(x)) <= 1e-9
+        assert abs(x @ (p.B() @ x) - 1.0) < 1e-10
+    for P_ in Ps:
+        P_.close()
 
 
 def test_eig_batch_workers_match_sequential(K, ctx):
