@@ -155,8 +155,9 @@ def gemm_traffic():
 
 
 def pmc_sample():
-    """One FP64 factorization of the bench pencil at sigma = PMC_SIGMA, then a plain
-    1 GiB device copy that calibrates FETCH_SIZE / WRITE_SIZE (run under rocprofv3 --pmc)."""
+    """One FP64 factorization of the bench pencil at sigma = PMC_SIGMA, a kept factor
+    with three solves and three SpMV of each kind, then a plain 1 GiB device copy
+    that calibrates FETCH_SIZE / WRITE_SIZE (run under rocprofv3 --pmc)."""
     import torch
     import pencilgen as pg
     import paper_1710_05134_amd as K
@@ -166,6 +167,11 @@ def pmc_sample():
     P = K.Pencil.from_pencilgen(ctx, p)
     nu = P.nu(PMC_SIGMA)
     log(f"factorization at sigma={PMC_SIGMA}: nu={nu}")
+    # a kept factor, three solves, three products B x and three fused A x, B x
+    F = P.factor(PMC_SIGMA)
+    pr = F.profile_solve(3)
+    F.close()
+    log(f"solve {pr['solve_s'] * 1e3:.2f} ms, B x {pr['spmv_b_s'] * 1e6:.1f} us")
     x = torch.empty(COPY_DOUBLES, dtype=torch.float64, device="cuda")
     x.fill_(1.0)
     y = torch.empty_like(x)
@@ -219,13 +225,31 @@ def summarize(stats_csv, fetch_csv, write_csv, command, pmc_command):
                 f"scale factors {f_fac:.3f} (fetch), {w_fac:.3f} (write).", "",
                 "| kernel | dispatches | read GB / dispatch | written GB / dispatch | total GB |",
                 "|---|---|---|---|---|"]
-        keys = sorted((nm for nm in fe if nm.startswith("void kth")), key=lambda nm: -fe[nm][0])
+        def short_name(nm):
+            return nm.replace("kth::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+        def base_name(nm):
+            return short_name(nm).split("<")[0].split("::")[-1]
+
+        keys = sorted((nm for nm in fe if "kth::" in nm), key=lambda nm: -fe[nm][0])
         for nm in keys:
             rf = fe[nm][0] * f_fac / fe[nm][1]
             rw = wr.get(nm, [0.0, 1])[0] * w_fac / max(wr.get(nm, [0.0, 1])[1], 1)
-            short = nm.replace("void kth::(anonymous namespace)::", "").split("(")[0]
+            short = short_name(nm)
             out.append(f"| `{short}` | {fe[nm][1]} | {rf / 1e9:.4f} | {rw / 1e9:.4f} | "
                        f"{(rf + rw) * fe[nm][1] / 1e9:.2f} |")
+        # the four solves of the sample (one warm-up + three timed) and its six SpMV
+        solve_k = ("k_gather", "k_solve_fwd", "k_lfwd_init", "k_lfwd_step", "k_solve_bwd",
+                   "k_lbwd_step", "k_lbwd_finish", "k_scatter")
+        tot = lambda nm: fe[nm][0] * f_fac + wr.get(nm, [0.0, 1])[0] * w_fac
+        sv = [nm for nm in keys if base_name(nm) in solve_k]
+        if sv:
+            out += ["", f"- solve_hbm_bytes_per_solve: {sum(tot(nm) for nm in sv) / 4:.6e}",
+                    "- solve_kernels: " + ", ".join(sorted({base_name(nm) for nm in sv}))]
+        sp = [nm for nm in keys if base_name(nm) == "k_spmv2"]
+        if sp:
+            out += [f"- spmv_hbm_bytes_per_dispatch: {sum(tot(nm) for nm in sp) / sum(fe[nm][1] for nm in sp):.6e}"
+                    f" (average of B x and the fused A x, B x)"]
         sch = [nm for nm in keys if "k_gemm_lt<256, double>" in nm]
         if sch:
             nm = sch[0]

@@ -183,9 +183,10 @@ typedef struct {
                              each shift aims, by linear interpolation of nu between the
                              bracket ends, at the count k - m_max/2 (lower end) or
                              k + m_max/2 - 1 (upper end), whichever end is farther from k,
-                             at a fraction of the bracket within [1/64, 63/64]; after the
-                             same end moved on two consecutive such steps the next shift
-                             is the midpoint.  Same stopping rule.  Needs multisection = 1. */
+                             at a fraction of the bracket within [1/64, 63/64]; after two
+                             consecutive such steps that each failed to halve nu_u - nu_l
+                             the next shift is the midpoint.  Same stopping rule.  Needs
+                             multisection = 1.                                             */
   int32_t si_block;       /* shift-and-invert Lanczos: 1 single vector (Alg. 3); p > 1 block
                              method with block size p; 0 (automatic) Alg. 3 for at most
                              3 m + 30 steps, then the block method with p = m (a multiple

@@ -154,26 +154,25 @@ def interp_shift(k, sl, su, nl, nu_, m_max):
 
 def stage2_interp(k, sl, su, nl, nu_, nu_of, log, m_max=20, tau_len=0.0):
     """Stage 2 with a safeguarded interpolating root-finder instead of the
-    midpoint: the shift comes from interp_shift, except that after the same end
-    of the bracket moved on two consecutive interpolated steps the next shift is
-    the midpoint (a bisection step), which bounds the worst case.  Same stopping
-    rule as Alg. 1' (at least one step; stop at nu_u - nu_l <= m_max, or below
-    tau_len)."""
+    midpoint: the shift comes from interp_shift, except that after two
+    consecutive interpolated steps that each failed to halve the count in the
+    bracket (nu_u - nu_l) the next shift is the midpoint (a bisection step), which
+    bounds the worst case.  Same stopping rule as Alg. 1' (at least one step;
+    stop at nu_u - nu_l <= m_max, or below tau_len)."""
     steps = 0
-    moved = []          # "l" / "u" per interpolated step since the last bisection
+    slow = []           # per interpolated step since the last bisection: gap not halved
     while True:
-        bisect = len(moved) >= 2 and moved[-1] == moved[-2]
+        bisect = len(slow) >= 2 and slow[-1] and slow[-2]
         sig = 0.5 * (sl + su) if bisect else interp_shift(k, sl, su, nl, nu_, m_max)
+        gap = nu_ - nl
         nu = nu_of(sig)
         log.append((sig, nu))
         steps += 1
         if k <= nu:
             su, nu_ = sig, nu
-            end = "u"
         else:
             sl, nl = sig, nu
-            end = "l"
-        moved = [] if bisect else moved + [end]
+        slow = [] if bisect else slow + [2 * (nu_ - nl) > gap]
         if nu_ - nl <= m_max:
             break
         if tau_len > 0 and (su - sl) < tau_len:

@@ -935,24 +935,25 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
     double tb = now_s();
     const int ms = std::max(1, o.multisection);
     m_eff = o.m_max > 0 ? o.m_max : auto_m_max(o.root_finder, t_fact_meas, t_solve_meas);
-    // interpolating stage 2: the same end of the bracket moving on two consecutive
-    // interpolated steps makes the next step a bisection (bounds the worst case)
-    char moved[2] = {0, 0};
-    int nmoved = 0;
+    // interpolating stage 2: two consecutive interpolated steps that each failed to
+    // halve the count in the bracket make the next step a bisection (bounds the
+    // worst case)
+    bool slow[2] = {false, false};
+    int nslow = 0;
     while (true) {
       if (ms == 1) {
-        const bool bisect = o.root_finder == 0 || (nmoved >= 2 && moved[0] == moved[1]);
+        const bool bisect = o.root_finder == 0 || (nslow >= 2 && slow[0] && slow[1]);
         double sig = bisect ? 0.5 * (sl + su) : interp_shift(k, sl, su, nl, nu_, m_eff);
+        const int64_t gap = nu_ - nl;
         int64_t nu = nu_checked(P, sig, 1e-3 * (su - sl), log, &nfac);
         s2++;
-        const char end = k <= nu ? 'u' : 'l';
         if (k <= nu) { su = sig; nu_ = nu; } else { sl = sig; nl = nu; }
         if (bisect) {
-          nmoved = 0;
+          nslow = 0;
         } else {
-          moved[0] = moved[1];
-          moved[1] = end;
-          nmoved++;
+          slow[0] = slow[1];
+          slow[1] = 2 * (nu_ - nl) > gap;
+          nslow++;
         }
       } else {
         std::vector<double> sg(ms);
