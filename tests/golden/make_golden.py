@@ -47,16 +47,21 @@ from oracle import three_stage as o3  # noqa: E402
 _SHARED = {}
 
 
+def _init_worker(cfg):
+    # each worker process builds the workload and the oracle's ordering itself
+    _SHARED["P"] = osp.prepare(pg.workload(cfg))
+
+
 def _count(sigma):
     st = osp.ldlt_stats(_SHARED["P"], sigma)
     return float(sigma), int(st.neg), int(st.zero)
 
 
-def _counts(P, sigmas, workers):
-    """Oracle inertia at several shifts, one process per shift (fork: the
-    prepared arrays are shared with the children)."""
-    _SHARED["P"] = P
-    with mp.get_context("fork").Pool(min(workers, len(sigmas))) as pool:
+def _counts(cfg, sigmas, workers):
+    """Oracle inertia at several shifts, one process per shift (fresh processes:
+    a forked child of a process that already ran threads can deadlock)."""
+    with mp.get_context("spawn").Pool(min(workers, len(sigmas)), initializer=_init_worker,
+                                       initargs=(cfg,)) as pool:
         return pool.map(_count, list(sigmas), chunksize=1)
 
 
@@ -129,7 +134,7 @@ def kth_oracle(cfg, workers, m_max=20, first_step=0.0015):
             eps, dlt = 1e-11 * nA, 1e-10 * nA
             pts = [lam - dlt, lam - eps, lam + eps, lam + dlt]
         t = time.perf_counter()
-        res = _counts(P, pts, workers)
+        res = _counts(cfg, pts, workers)
         state["counts"].extend([list(r) for r in res])
         state.setdefault("rounds", []).append(dict(phase=state["phase"], sigmas=pts,
                                                    seconds=time.perf_counter() - t))
