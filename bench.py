@@ -273,8 +273,11 @@ def main():
                     help="stage-2 stopping count (0: chosen by the library's cost model)")
     ap.add_argument("--root-finder", type=int, default=1, choices=[0, 1],
                     help="stage 2: 0 bisection (Alg. 1'), 1 safeguarded interpolation")
+    ap.add_argument("--b-solver", type=int, default=1, choices=[0, 1],
+                    help="stage-1 B-solves: 0 LDL^T factor of B, 1 Jacobi CG when B is "
+                         "strictly diagonally dominant")
     ap.add_argument("--skip", nargs="*", default=[],
-                    choices=["stage2_other", "hbm", "fp32_ir", "c3a", "c3b"],
+                    choices=["stage2_other", "b_other", "hbm", "fp32_ir", "c3a", "c3b"],
                     help="extra legs to leave out")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="one factorization + a 1 GiB calibration copy, for rocprofv3 --pmc")
@@ -311,7 +314,7 @@ def main():
     ana = K.kth_analyze(p.rowptr, p.col)
     log(f"pencil ready in {t_cold:.2f} s (analysis flops {ana['flops']:.3e}, max front {ana['max_front']:.0f})")
     opts = K.default_opts(start_vectors=pg.start_vectors(p.n), root_finder=args.root_finder,
-                          m_max=args.m_max)
+                          m_max=args.m_max, b_solver=args.b_solver)
 
     for w in range(args.warmup):
         lam, _, info = P.eig(p.k, opts=opts, want_x=False)
@@ -370,6 +373,9 @@ def main():
             "stage1_steps": info["stage1_steps"], "bisection_steps": info["bisection_steps"],
             "si_steps": info["si_steps"],
             "m_max_used": info["m_max_used"],
+            "b_solver": "Jacobi-preconditioned CG on B (b_solver=1)" if info["b_cg_iterations"] else
+                        "LDL^T factor of B",
+            "b_cg_iterations": info["b_cg_iterations"],
             "stage2": "bisection (Alg. 1')" if args.root_finder == 0 else
                       "safeguarded interpolation of the count (root_finder=1)",
             "min_pivot_rel": info["min_pivot_rel"], "max_abs_l": info["max_abs_l"],
@@ -433,7 +439,7 @@ def main():
         # the same run with the other stage-2 rule
         other = 1 - args.root_finder
         oo = K.default_opts(start_vectors=pg.start_vectors(p.n), root_finder=other,
-                            m_max=20 if other == 0 else args.m_max)
+                            m_max=20 if other == 0 else args.m_max, b_solver=args.b_solver)
         P.eig(p.k, opts=oo, want_x=False)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -444,10 +450,24 @@ def main():
                 "factorizations": io["n_factorizations"], "stage2_steps": io["bisection_steps"],
                 "t_stage2_s": io["t_task"][4]}
 
+    def b_leg():
+        # the same run with the other stage-1 B-solve
+        ob = K.default_opts(start_vectors=pg.start_vectors(p.n), root_finder=args.root_finder,
+                            m_max=args.m_max, b_solver=1 - args.b_solver)
+        P.eig(p.k, opts=ob, want_x=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lb, _, ib = P.eig(p.k, opts=ob, want_x=False)
+        torch.cuda.synchronize()
+        return {"b_solver": 1 - args.b_solver, "time_s": time.perf_counter() - t, "lambda_k": lb,
+                "abs_diff": abs(lb - lam), "k_validated": ib["k_validated"],
+                "factorizations": ib["n_factorizations"], "b_cg_iterations": ib["b_cg_iterations"],
+                "t_b_factor_s": ib["t_task"][1]}
+
     def fp32_leg():
         # the same run with the shift-and-invert factor in FP32 + FP64 refinement
         o32 = K.default_opts(start_vectors=pg.start_vectors(p.n), si_precision=K.KTH_FP32_IR,
-                             root_finder=args.root_finder, m_max=args.m_max)
+                             root_finder=args.root_finder, m_max=args.m_max, b_solver=args.b_solver)
         P.eig(p.k, opts=o32, want_x=False)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -520,6 +540,7 @@ def main():
                 "factorizations": sum(r[3]["n_factorizations"] for r in res)}
 
     leg("stage2_other", stage2_leg)
+    leg("b_other", b_leg)
     leg("hbm", hbm_leg)
     leg("fp32_ir", fp32_leg)
     leg("c3a", c3a_leg)

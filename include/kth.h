@@ -195,6 +195,11 @@ typedef struct {
                              with more than m_max eigenvalues.  The block method validates
                              overlapping bounds as a cluster (see kth_info.si_block).       */
   int32_t n_start_vectors;  /* rows of start_vectors (0: 4)                                  */
+  int32_t b_solver;       /* stage-1 B-solves: 0 the LDL^T factor of B (task (ii)); 1 when B is
+                             strictly diagonally dominant with a positive diagonal (positive
+                             definite by Gershgorin's theorem, no factor needed), Jacobi-
+                             preconditioned conjugate gradients to a relative residual of
+                             1e-14, else the factor                                        */
 } kth_opts;
 
 typedef struct {
@@ -226,6 +231,8 @@ typedef struct {
   int32_t si_block;           /* block size of the shift-and-invert Lanczos that ran last (1:
                                  Alg. 3); si_steps counts the steps of both methods         */
   int64_t m_max_used;         /* stage-2 stopping count in effect (opts.m_max, or the model's) */
+  int32_t b_cg_iterations;    /* conjugate-gradient steps of the B-solves (b_solver = 1)       */
+  int32_t pad1;
 } kth_info;
 
 void kth_opts_default(kth_opts* o);

@@ -39,7 +39,7 @@ class kth_opts(C.Structure):
                 ("seed", C.c_uint64), ("si_precision", C.c_int), ("start_vectors", C.c_void_p),
                 ("warm_interval", C.c_void_p), ("warm_counts", C.c_void_p), ("ir_tol", C.c_double),
                 ("batch_workers", C.c_int32), ("root_finder", C.c_int32), ("si_block", C.c_int32),
-                ("n_start_vectors", C.c_int32)]
+                ("n_start_vectors", C.c_int32), ("b_solver", C.c_int32)]
 
 
 class kth_info(C.Structure):
@@ -56,7 +56,8 @@ class kth_info(C.Structure):
                 ("si_precision", C.c_int32), ("ir_steps", C.c_int32), ("ir_fallback", C.c_int32),
                 ("ir_max_berr", C.c_double), ("max_abs_l", C.c_double),
                 ("weak_pivot_nudges", C.c_int32), ("weak_pivot_kept", C.c_int32),
-                ("stage1_restarts", C.c_int32), ("si_block", C.c_int32), ("m_max_used", C.c_int64)]
+                ("stage1_restarts", C.c_int32), ("si_block", C.c_int32), ("m_max_used", C.c_int64),
+                ("b_cg_iterations", C.c_int32), ("pad1", C.c_int32)]
 
     def as_dict(self) -> dict:
         d = {}

@@ -210,6 +210,12 @@ __global__ void k_max_partials(int nblk, const double* __restrict__ partial, dou
   *out = t;
 }
 
+__global__ void k_vmul(int64_t n, const double* __restrict__ d, const double* __restrict__ x,
+                       double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    y[i] = d[i] * x[i];
+}
+
 __global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* y) {
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
     y[i] = fma(a, x[i], y[i]);
@@ -438,6 +444,10 @@ void absmax(int64_t n, const double* x, double* partial, double* out, hipStream_
   const int nb = multidot_blocks(n);
   hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(NT), 0, s, n, x, partial);
   hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(64), 0, s, nb, partial, out);
+}
+
+void vmul(int64_t n, const double* d, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_vmul, dim3(blocks_for(n, NT * 4)), dim3(NT), 0, s, n, d, x, y);
 }
 
 void axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {

@@ -38,6 +38,8 @@ void shifted_residual(int64_t n, const int64_t* rowptr, const int32_t* col, cons
 // *out = max_i |x_i| (partial: multidot_blocks(n) doubles)
 void absmax(int64_t n, const double* x, double* partial, double* out, hipStream_t s);
 void axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);
+// y = d .* x (elementwise)
+void vmul(int64_t n, const double* d, const double* x, double* y, hipStream_t s);
 // out[map[i]] = in[i], i < m (device arrays)
 void scatter_values(int64_t m, const int64_t* map, const double* in, double* out, hipStream_t s);
 void hf_gradient(int64_t n, const int64_t* rowptr, const int32_t* col, const double* x, double g,

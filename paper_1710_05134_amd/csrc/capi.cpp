@@ -74,6 +74,7 @@ void check_opts(const kth_opts& o) {
   if (o.root_finder != 0 && o.root_finder != 1) throw Error(KTH_EINVAL, "root_finder must be 0 or 1");
   if (o.si_block < 0 || o.si_block > 64) throw Error(KTH_EINVAL, "si_block must be in [0, 64]");
   if (o.n_start_vectors < 0) throw Error(KTH_EINVAL, "n_start_vectors must be >= 0");
+  if (o.b_solver != 0 && o.b_solver != 1) throw Error(KTH_EINVAL, "b_solver must be 0 or 1");
   if (o.root_finder == 1 && o.multisection != 1)
     throw Error(KTH_EINVAL, "the interpolating root-finder takes one shift per step (multisection = 1)");
 }

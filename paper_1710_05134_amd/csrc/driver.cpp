@@ -835,17 +835,66 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   std::vector<double> hv;
 
   // ---- task (ii): factor of B (its inertia must be (0, 0, n)) ----
+  // With b_solver = 1 and B strictly diagonally dominant with a positive diagonal
+  // (symmetric positive definite by Gershgorin's theorem), B is not factored:
+  // the stage-1 B-solves run Jacobi-preconditioned conjugate gradients.
+  const bool b_cg = o.b_solver == 1 && P.b_diag_dominant;
   double t0 = now_s();
   // the factor of B and the shift-and-invert factor are kept by the pencil, so
   // later calls replay their captured launch sequences
   if (!P.fb) { P.fb.reset(new NumFactor()); P.fb->replay = true; }
   NumFactor& FB = *P.fb;
-  factor_alloc(P, FB);
-  factor_enqueue(P, FB, 0.0, true);
-  factor_read_stats(P, FB);
-  nfac++;
-  if (FB.hs.neg != 0 || FB.hs.zero != 0) throw Error(KTH_ENOTPD, "B is not positive definite");
+  if (!b_cg) {
+    factor_alloc(P, FB);
+    factor_enqueue(P, FB, 0.0, true);
+    factor_read_stats(P, FB);
+    nfac++;
+    if (FB.hs.neg != 0 || FB.hs.zero != 0) throw Error(KTH_ENOTPD, "B is not positive definite");
+  }
   t_task[1] = now_s() - t0;
+  // x = B^{-1} rhs (device vectors): the factor's solve, or conjugate gradients
+  // to a relative residual of 1e-14
+  DBuf<double> cg_r, cg_z, cg_p, cg_q;
+  int cg_iters = 0;
+  auto bsolve = [&](const double* rhs, double* x) {
+    if (!b_cg) {
+      solve_enqueue_f(P, FB, rhs, x);
+      return;
+    }
+    if (!cg_r.p) {
+      cg_r.alloc(c, n); cg_z.alloc(c, n); cg_p.alloc(c, n); cg_q.alloc(c, n);
+    }
+    const double* dinv = P.b_dinv.get();
+    double* r = cg_r.get();
+    double* z = cg_z.get();
+    double* p = cg_p.get();
+    double* q = cg_q.get();
+    vmul(n, dinv, rhs, x, st);                         // x0 = D^{-1} rhs
+    spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), x, nullptr, q, st);
+    KTH_HIP(hipMemcpyAsync(r, rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    axpy(n, -1.0, q, r, st);
+    vmul(n, dinv, r, z, st);
+    KTH_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    const double bb = dot_dev(W, rhs, rhs);
+    double rz = dot_dev(W, r, z);
+    for (int it = 0;; it++) {
+      if (it >= 1000) throw Error(KTH_ENOCONV, "conjugate gradients on B did not converge");
+      spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), p, nullptr, q, st);
+      const double pq = dot_dev(W, p, q);
+      if (!(pq > 0)) throw Error(KTH_ENOTPD, "B is not positive definite (conjugate gradients)");
+      const double al = rz / pq;
+      axpy(n, al, p, x, st);
+      axpy(n, -al, q, r, st);
+      cg_iters++;
+      const double rr = dot_dev(W, r, r);
+      if (rr <= 1e-28 * bb) break;
+      vmul(n, dinv, r, z, st);
+      const double rz2 = dot_dev(W, r, z);
+      scale_copy(n, rz2 / rz, p, p, st);
+      axpy(n, 1.0, z, p, st);
+      rz = rz2;
+    }
+  };
 
   double sl, su;
   int64_t nl, nu_;
@@ -879,15 +928,15 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
         // A v_j, alpha_j, w = B^{-1} A v_j
         spmv2(n, P.rowptr.get(), P.col.get(), P.aval.get(), P.bval.get(), W.v(j - 1), W.ya.get(), nullptr, st);
         al.push_back(dot_dev(W, W.v(j - 1), W.ya.get()));
-        if (j == 1 && o.m_max == 0 && o.root_finder == 0) {
+        if (j == 1 && o.m_max == 0 && o.root_finder == 0 && !b_cg) {
           // time of one solve with a factor of the pencil's structure (cost model)
           c->sync();
           const double ts0 = now_s();
-          solve_enqueue_f(P, FB, W.ya.get(), W.w.get());
+          bsolve(W.ya.get(), W.w.get());
           c->sync();
           t_solve_meas = now_s() - ts0;
         } else {
-          solve_enqueue_f(P, FB, W.ya.get(), W.w.get());
+          bsolve(W.ya.get(), W.w.get());
         }
         KTH_HIP(hipMemcpyAsync(W.Bw.get(), W.ya.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         for (int pass = 0; pass < 2; pass++) {   // CGS2 in the B inner product: h = V^T (B w)
@@ -1237,6 +1286,7 @@ kth_status three_stage(Pencil& P, int64_t k, const kth_opts& o, double* lambda, 
   info->weak_pivot_kept = log.weak_kept;
   info->stage1_restarts = s1_restarts;
   info->m_max_used = m_eff;
+  info->b_cg_iterations = cg_iters;
   info->n_factorizations = nfac;
   info->flops_factor = P.S.flops;
   for (int q = 0; q < 7; q++) info->t_task[q] = t_task[q];

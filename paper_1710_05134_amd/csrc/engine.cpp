@@ -404,6 +404,25 @@ void pencil_init(Pencil& P, Ctx* ctx, int64_t n, const int64_t* arp, const int32
   ctx->sync();
 }
 
+// B strictly diagonally dominant with a positive diagonal (then symmetric positive
+// definite by Gershgorin's theorem), and 1 / diag(B) on the device for the Jacobi
+// preconditioner of the conjugate-gradient B-solve.
+static void b_dominance(Pencil& P, const double* b) {
+  std::vector<double> dinv(P.n, 0.0);
+  bool dd = true;
+  for (int64_t i = 0; i < P.n; i++) {
+    double di = 0, off = 0;
+    for (int64_t q = P.h_rowptr[i]; q < P.h_rowptr[i + 1]; q++) {
+      if (P.h_col[q] == i) di = b[q];
+      else off += std::fabs(b[q]);
+    }
+    if (!(di > off)) dd = false;
+    dinv[i] = di != 0 ? 1.0 / di : 0.0;
+  }
+  P.b_diag_dominant = dd;
+  P.b_dinv.upload(P.ctx, dinv);
+}
+
 void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_ptrs) {
   Ctx* c = P.ctx;
   const size_t bytes = P.nnz * sizeof(double);
@@ -412,6 +431,7 @@ void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_
     KTH_HIP(hipMemcpyAsync(P.bval.get(), b, bytes, hipMemcpyHostToDevice, c->stream));
     P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), a);
     P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), b);
+    b_dominance(P, b);
     c->sync();
     return;
   }
@@ -423,6 +443,7 @@ void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_
     KTH_HIP(hipMemcpyAsync(P.bval.get(), ub.data(), bytes, hipMemcpyHostToDevice, c->stream));
     P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), ua.data());
     P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), ub.data());
+    b_dominance(P, ub.data());
     c->sync();   // the host staging arrays go out of scope
     return;
   }
@@ -442,6 +463,8 @@ void pencil_set_values(Pencil& P, const double* a, const double* b, bool device_
   c->sync();
   P.normA_inf = csr_norm_inf(P.n, P.h_rowptr.data(), ha.data());
   P.normB_inf = csr_norm_inf(P.n, P.h_rowptr.data(), hb.data());
+  b_dominance(P, hb.data());
+  c->sync();
 }
 
 static void ensure_workspace(Pencil& P, int nb) {

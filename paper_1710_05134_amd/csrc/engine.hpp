@@ -130,6 +130,8 @@ struct Pencil {
   std::vector<int64_t> h_amap, h_bmap;
   DBuf<int64_t> d_amap, d_bmap;
   double normA_inf = 0, normB_inf = 0;
+  bool b_diag_dominant = false;   // B strictly diagonally dominant, positive diagonal
+  DBuf<double> b_dinv;            // 1 / diag(B)
   // device CSR and values
   DBuf<int64_t> rowptr;
   DBuf<int32_t> col;
