@@ -350,6 +350,12 @@ def main():
         f"{gm['bytes'] / gm_s / 1e9:.0f} GB/s algorithmic; classes "
         + ", ".join(f"{k} {statistics.median(pr[k]['seconds'] for pr in profs) * 1e3:.1f} ms"
                     for k in classes))
+    cb_s = statistics.median(pr["gemm_cb"]["seconds"] for pr in profs)
+    cb = profs[0]["gemm_cb"]
+    ll_s = gm_s - cb_s
+    log(f"  contribution blocks {cb_s * 1e3:.1f} ms in {cb['launches']} launches = "
+        f"{cb['flops'] / max(cb_s, 1e-12) / 1e12:.2f} TFLOP/s; left-looking "
+        f"{ll_s * 1e3:.1f} ms = {(gm['flops'] - cb['flops']) / max(ll_s, 1e-12) / 1e12:.2f} TFLOP/s")
 
     out = {
         "metric": METRIC,
@@ -403,6 +409,10 @@ def main():
             "flops_per_launch": per_launch_flops,
             "avg_launch_us": avg_launch_s * 1e6,
             "classes_ms": {k: statistics.median(pr[k]["seconds"] for pr in profs) * 1e3 for k in classes},
+            "gemm_split": {"contribution_blocks_ms": cb_s * 1e3,
+                           "contribution_blocks_tflops": cb["flops"] / max(cb_s, 1e-12) / 1e12,
+                           "left_looking_ms": ll_s * 1e3,
+                           "left_looking_tflops": (gm["flops"] - cb["flops"]) / max(ll_s, 1e-12) / 1e12},
         },
     }
 

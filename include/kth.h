@@ -268,7 +268,9 @@ kth_status kth_eig_backward(kth_pencil p, double lambda, const double* x, double
  *   assembly, pivot tiles, panel solves, left-looking and contribution-block
  *   products k_gemm_lt, split-depth reductions): seconds, dense operation count,
  *   number of launches, algorithmic HBM bytes (class 4 only: each output entry read
- *   and written once, each operand row read once); [27] nu(sigma). */
+ *   and written once, each operand row read once); [27] nu(sigma); with nout >= 32,
+ *   [28 .. 31] the contribution-block launches' share of class 4 (seconds,
+ *   operation count, launches, algorithmic bytes). */
 kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t nout);
 
 /* Measurement of the bandwidth-bound steps with a kept factor f: HIP events on the

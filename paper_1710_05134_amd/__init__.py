@@ -224,13 +224,15 @@ class Pencil:
 
     def profile_factor(self, sigma: float) -> dict:
         """One factorization with per-kernel-class event timing (see kth.h)."""
-        out = np.zeros(28)
-        _check(lib().kth_profile_factor(self.h, float(sigma), _p(out, C.c_double), 28), self.ctx.h)
+        out = np.zeros(32)
+        _check(lib().kth_profile_factor(self.h, float(sigma), _p(out, C.c_double), 32), self.ctx.h)
         names = ("small", "assemble", "tile", "trsm", "gemm", "reduce")
         d = dict(total_s=out[0], flops=out[1], flops_padded=out[2], nu=int(out[27]))
         for c, nm in enumerate(names):
             d[nm] = dict(seconds=out[3 + 4 * c], flops=out[4 + 4 * c], launches=int(out[5 + 4 * c]),
                          bytes=out[6 + 4 * c])
+        # the contribution-block launches' share of "gemm"
+        d["gemm_cb"] = dict(seconds=out[28], flops=out[29], launches=int(out[30]), bytes=out[31])
         return d
 
     def factor(self, sigma: float, precision: int = KTH_FP64) -> "Factor":

@@ -447,6 +447,12 @@ kth_status kth_profile_factor(kth_pencil p, double sigma, double* out, int32_t n
       out[6 + 4 * c] = prof.bytes[c];
     }
     out[27] = (double)F.hs.neg;
+    if (nout >= 32) {
+      out[28] = prof.cb_time;
+      out[29] = prof.cb_flops;
+      out[30] = (double)prof.cb_launches;
+      out[31] = prof.cb_bytes;
+    }
   });
 }
 

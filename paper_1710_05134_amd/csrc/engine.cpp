@@ -518,7 +518,8 @@ struct ProfScope {
   FactorProfile* p;
   hipStream_t st;
   int cls;
-  ProfScope(FactorProfile* pr, hipStream_t s, int c, double flops, double bytes = 0.0)
+  ProfScope(FactorProfile* pr, hipStream_t s, int c, double flops, double bytes = 0.0,
+            bool cb = false)
       : p(pr), st(s), cls(c) {
     if (!p) return;
     hipEvent_t e;
@@ -526,9 +527,11 @@ struct ProfScope {
     KTH_HIP(hipEventRecord(e, st));
     p->ev.push_back(e);
     p->cls.push_back(c);
+    p->cb.push_back(cb ? 1 : 0);
     p->flops[c] += flops;
     p->bytes[c] += bytes;
     p->launches[c]++;
+    if (cb) { p->cb_flops += flops; p->cb_bytes += bytes; p->cb_launches++; }
   }
   ~ProfScope() {
     if (!p) return;
@@ -731,7 +734,7 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
           fl_cb += 2.0 * ns * nu * (nu + 1) / 2;
           by_cb += 16.0 * nu * (nu + 1) / 2 + 2.0 * 8.0 * ns * nu;   // C once; L_u and W_u once
         }
-      ProfScope ps(prof, st, PROF_GEMM, fl_cb, by_cb);
+      ProfScope ps(prof, st, PROF_GEMM, fl_cb, by_cb, true);
       launch_gemm_lt(P.meta, reinterpret_cast<const Int2*>(sched + lp.cb_off), lp.cb_cnt, 0, 2, 1, 0,
                      bt, nb, Lf, Uf, Wf, Pf, st);
     }
@@ -751,6 +754,7 @@ void factor_profile_finish(Pencil& P, FactorProfile& prof) {
     float ms = 0;
     KTH_HIP(hipEventElapsedTime(&ms, prof.ev[q], prof.ev[q + 1]));
     prof.time[prof.cls[q / 2]] += ms * 1e-3;
+    if (prof.cb[q / 2]) prof.cb_time += ms * 1e-3;
   }
   if (prof.ev.size() >= 2) {
     float ms = 0;

@@ -203,6 +203,10 @@ struct FactorProfile {
   double flops[PROF_NCLASS] = {0};  // dense-front operation counts of the launches
   double bytes[PROF_NCLASS] = {0};  // algorithmic HBM bytes of the launches (where stated)
   int64_t launches[PROF_NCLASS] = {0};
+  // the contribution-block share of PROF_GEMM (seconds, operations, launches, bytes)
+  std::vector<char> cb;             // per event pair: a contribution-block launch
+  double cb_time = 0, cb_flops = 0, cb_bytes = 0;
+  int64_t cb_launches = 0;
   double total = 0;                 // seconds, first to last event
   ~FactorProfile();
 };
