@@ -48,6 +48,9 @@ constexpr int kSolveChunk = 256;
 constexpr int kSolveRows = 256;
 // Schur-update output tile.
 constexpr int kTile = 64;
+// fronts whose contribution block has at least this many rows update it on
+// 128 x 128 tiles (k_gemm_cb128)
+constexpr int kCb128MinNu = 384;
 // depth segment of a split left-looking update of the rows below a pivot tile
 constexpr int kSegK = 256;
 // the diagonal block's update (one output tile per front, on the critical path)
@@ -102,6 +105,10 @@ template <typename T>
 void launch_gemm_lt(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int mode,
                     int nseg, int segk, const Batch& bt, int nb, T* L, T* U, const T* W, T* part,
                     hipStream_t s);
+// Contribution-block update on lower 128 x 128 tiles, tasks (front, tile number).
+template <typename T>
+void launch_gemm_cb128(const FrontMeta& M, const Int2* tasks, int32_t count, const Batch& bt, int nb,
+                       T* L, T* U, const T* W, hipStream_t s);
 template <typename T>
 void launch_gemm_reduce(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int nseg,
                         const Batch& bt, int nb, T* L, const T* part, hipStream_t s);

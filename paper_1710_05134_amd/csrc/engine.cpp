@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace kth {
@@ -122,8 +123,20 @@ static double csr_norm_inf(int64_t n, const int64_t* rp, const double* v) {
   return m;
 }
 
+// Contribution blocks with at least this many rows go to 128 x 128 tiles
+// (kCb128MinNu; the environment variable KTH_CB128_MIN_NU overrides it, read when
+// a pencil is created: a huge value keeps every block on 64 x 64 tiles).
+static int64_t cb128_min_nu() {
+  const char* e = std::getenv("KTH_CB128_MIN_NU");
+  if (!e || !*e) return kCb128MinNu;
+  const long long v = std::atoll(e);
+  return v < 1 ? 1 : (int64_t)v;
+}
+
 static void build_schedule(Pencil& P) {
   const Symbolic& S = P.S;
+  const int64_t nu_big = cb128_min_nu();
+  P.cb128_min_nu = nu_big;
   std::vector<int32_t> sched;
   auto align2 = [&]() { if (sched.size() & 1) sched.push_back(0); };
   std::vector<std::vector<int32_t>> bylevel(S.nlevels);
@@ -209,15 +222,24 @@ static void build_schedule(Pencil& P) {
         P.psize = std::max<int64_t>(P.psize, (int64_t)sp.ll_diag_cnt * sp.ll_nseg_d * kTile * kTile);
       lp.steps.push_back(sp);
     }
-    // contribution blocks: lower kTile x kTile tiles of each nu x nu block (depth ns)
+    // contribution blocks: lower tiles of each nu x nu block (depth ns), 64 x 64 or,
+    // for nu >= nu_big, 128 x 128
     align2();
     lp.cb_off = (int32_t)sched.size();
     for (int32_t s : large) {
       const int64_t nu = S.nf(s) - S.ns(s), T = (nu + kTile - 1) / kTile;
-      if (T * (T + 1) / 2 > INT32_MAX) throw Error(KTH_EINVAL, "front too large for the tile schedule");
+      if (nu >= nu_big) continue;
       for (int64_t tl = 0; tl < T * (T + 1) / 2; tl++) { sched.push_back(s); sched.push_back((int32_t)tl); }
     }
     lp.cb_cnt = (int32_t)((sched.size() - lp.cb_off) / 2);
+    lp.cb128_off = (int32_t)sched.size();
+    for (int32_t s : large) {
+      const int64_t nu = S.nf(s) - S.ns(s), T = (nu + 127) / 128;
+      if (nu < nu_big) continue;
+      if (T * (T + 1) / 2 > INT32_MAX) throw Error(KTH_EINVAL, "front too large for the tile schedule");
+      for (int64_t tl = 0; tl < T * (T + 1) / 2; tl++) { sched.push_back(s); sched.push_back((int32_t)tl); }
+    }
+    lp.cb128_cnt = (int32_t)((sched.size() - lp.cb128_off) / 2);
   }
   std::vector<int64_t> pbase(S.nsup, -1);
   P.splan.partial_half = 0;
@@ -725,18 +747,32 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
         }
       }
     }
+    // contribution blocks, operation counts and algorithmic bytes: C once; L_u and
+    // W_u once
+    auto cb_cost = [&](bool big, double& fl, double& by) {
+      fl = by = 0;
+      if (!prof) return;
+      for (int32_t q = 0; q < lp.large_cnt; q++) {
+        const int32_t s = hs[lp.large_off + q];
+        const double ns = (double)S.ns(s), nu = (double)(S.nf(s) - S.ns(s));
+        if ((nu >= (double)P.cb128_min_nu) != big) continue;
+        fl += 2.0 * ns * nu * (nu + 1) / 2;
+        by += 16.0 * nu * (nu + 1) / 2 + 2.0 * 8.0 * ns * nu;
+      }
+    };
     if (lp.cb_cnt > 0) {
-      double fl_cb = 0, by_cb = 0;
-      if (prof)
-        for (int32_t q = 0; q < lp.large_cnt; q++) {
-          const int32_t s = hs[lp.large_off + q];
-          const double ns = (double)S.ns(s), nu = (double)(S.nf(s) - S.ns(s));
-          fl_cb += 2.0 * ns * nu * (nu + 1) / 2;
-          by_cb += 16.0 * nu * (nu + 1) / 2 + 2.0 * 8.0 * ns * nu;   // C once; L_u and W_u once
-        }
+      double fl_cb, by_cb;
+      cb_cost(false, fl_cb, by_cb);
       ProfScope ps(prof, st, PROF_GEMM, fl_cb, by_cb, true);
       launch_gemm_lt(P.meta, reinterpret_cast<const Int2*>(sched + lp.cb_off), lp.cb_cnt, 0, 2, 1, 0,
                      bt, nb, Lf, Uf, Wf, Pf, st);
+    }
+    if (lp.cb128_cnt > 0) {
+      double fl_cb, by_cb;
+      cb_cost(true, fl_cb, by_cb);
+      ProfScope ps(prof, st, PROF_GEMM, fl_cb, by_cb, true);
+      launch_gemm_cb128(P.meta, reinterpret_cast<const Int2*>(sched + lp.cb128_off), lp.cb128_cnt, bt,
+                        nb, Lf, Uf, Wf, st);
     }
   }
   KTH_HIP(hipGetLastError());

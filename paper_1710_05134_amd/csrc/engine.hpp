@@ -114,6 +114,7 @@ struct LevelPlan {
   int32_t init_off = 0, init_cnt = 0;
   int32_t large_off = 0, large_cnt = 0;
   int32_t cb_off = 0, cb_cnt = 0;    // Int2 (front, lower tile) of the contribution blocks
+  int32_t cb128_off = 0, cb128_cnt = 0;  // the same on 128 x 128 tiles (nu >= cb128_min_nu)
   std::vector<StepPlan> steps;
 };
 
@@ -143,6 +144,7 @@ struct Pencil {
   DBuf<int64_t> d_iptr;
   FrontMeta meta{};
   std::vector<LevelPlan> levels;
+  int64_t cb128_min_nu = 0;          // contribution blocks of >= this many rows: 128 x 128 tiles
   std::vector<int32_t> h_sched;   // host copy of the schedule array
   SolvePlan splan;
   int64_t wsize = 0;   // W = L D workspace (panel-shaped) elements per factorization

@@ -1150,6 +1150,189 @@ __global__ __launch_bounds__(NT) void k_gemm_reduce(FrontMeta M, const Int2* tas
   Cb[i + (int64_t)j * nf] -= sum;
 }
 
+// The operand values of one 8-deep chunk of k_gemm_cb128: av[s][a] at byte address
+// ba + a * 16 rows + s * 4 columns, bv likewise from bb, in LDS with a column
+// stride of 144 elements (128 rows + 16 of padding: consecutive columns start on
+// different banks).  One asm block issues the 16 reads and waits for them.
+__device__ __forceinline__ void lds_read_cb128(uint32_t ba, uint32_t bb, double (&av)[2][4],
+                                               double (&bv)[2][4]) {
+  asm volatile(
+      "ds_read_b64 %0, %16\n ds_read_b64 %1, %16 offset:128\n"
+      "ds_read_b64 %2, %16 offset:256\n ds_read_b64 %3, %16 offset:384\n"
+      "ds_read_b64 %4, %16 offset:4608\n ds_read_b64 %5, %16 offset:4736\n"
+      "ds_read_b64 %6, %16 offset:4864\n ds_read_b64 %7, %16 offset:4992\n"
+      "ds_read_b64 %8, %17\n ds_read_b64 %9, %17 offset:128\n"
+      "ds_read_b64 %10, %17 offset:256\n ds_read_b64 %11, %17 offset:384\n"
+      "ds_read_b64 %12, %17 offset:4608\n ds_read_b64 %13, %17 offset:4736\n"
+      "ds_read_b64 %14, %17 offset:4864\n ds_read_b64 %15, %17 offset:4992\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(av[0][0]), "=&v"(av[0][1]), "=&v"(av[0][2]), "=&v"(av[0][3]), "=&v"(av[1][0]),
+        "=&v"(av[1][1]), "=&v"(av[1][2]), "=&v"(av[1][3]), "=&v"(bv[0][0]), "=&v"(bv[0][1]),
+        "=&v"(bv[0][2]), "=&v"(bv[0][3]), "=&v"(bv[1][0]), "=&v"(bv[1][1]), "=&v"(bv[1][2]),
+        "=&v"(bv[1][3])
+      : "v"(ba), "v"(bb)
+      : "memory");
+}
+__device__ __forceinline__ void lds_read_cb128(uint32_t ba, uint32_t bb, float (&av)[2][4],
+                                               float (&bv)[2][4]) {
+  asm volatile(
+      "ds_read_b32 %0, %16\n ds_read_b32 %1, %16 offset:64\n"
+      "ds_read_b32 %2, %16 offset:128\n ds_read_b32 %3, %16 offset:192\n"
+      "ds_read_b32 %4, %16 offset:2304\n ds_read_b32 %5, %16 offset:2368\n"
+      "ds_read_b32 %6, %16 offset:2432\n ds_read_b32 %7, %16 offset:2496\n"
+      "ds_read_b32 %8, %17\n ds_read_b32 %9, %17 offset:64\n"
+      "ds_read_b32 %10, %17 offset:128\n ds_read_b32 %11, %17 offset:192\n"
+      "ds_read_b32 %12, %17 offset:2304\n ds_read_b32 %13, %17 offset:2368\n"
+      "ds_read_b32 %14, %17 offset:2432\n ds_read_b32 %15, %17 offset:2496\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(av[0][0]), "=&v"(av[0][1]), "=&v"(av[0][2]), "=&v"(av[0][3]), "=&v"(av[1][0]),
+        "=&v"(av[1][1]), "=&v"(av[1][2]), "=&v"(av[1][3]), "=&v"(bv[0][0]), "=&v"(bv[0][1]),
+        "=&v"(bv[0][2]), "=&v"(bv[0][3]), "=&v"(bv[1][0]), "=&v"(bv[1][1]), "=&v"(bv[1][2]),
+        "=&v"(bv[1][3])
+      : "v"(ba), "v"(bb)
+      : "memory");
+}
+
+// ---------------------------------------------------------------------------
+// Large fronts with big contribution blocks: the update
+//   U(i, j) -= sum_{q < ns} L(ns + i, q) W(ns + j, q),   i >= j,
+// on lower 128 x 128 tiles (tile tl = bi (bi + 1) / 2 + bj), twice the operand
+// reuse of the 64 x 64 tiles of k_gemm_lt.  Four waves as 2 x 2 blocks of 64 x 64
+// (4 x 4 MFMA blocks of 16 x 16 each).  The depth is walked in chunks of 8 columns
+// loaded straight from global memory into a ring of four LDS buffers per operand
+// (18 KB per chunk for FP64), three chunks in flight while one feeds the matrix
+// cores; two workgroups fit one CU.  Each output entry receives the same products
+// in the same order as in k_gemm_lt (4-deep MFMA steps in increasing depth).
+// ---------------------------------------------------------------------------
+template <int NT, typename T>
+__global__ __launch_bounds__(NT, 2) void k_gemm_cb128(FrontMeta M, const Int2* tasks, Batch bt,
+                                                      T* L, T* U, const T* W) {
+  {
+    const int64_t bidx = blockIdx.y;
+    L += bidx * bt.sL; U += bidx * bt.sU; W += bidx * bt.sW;
+  }
+  constexpr int TB = 128;        // output tile edge
+  constexpr int CS = TB + 16;    // LDS column stride (elements)
+  constexpr int KC = 8;          // depth chunk staged through LDS
+  constexpr int NS = 4;          // ring of chunk buffers
+  __shared__ T As[NS][CS * KC];
+  __shared__ T Bs[NS][CS * KC];
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a, tl = tk.b;
+  const FrontRef<T> f = front_ref<T>(M, s, L, U);
+  const T* Lp = f.Lp;
+  const T* Wp = W + M.lptr[s];
+  int bi = (int)((sqrt(8.0 * tl + 1.0) - 1.0) * 0.5);
+  while ((bi + 1) * (bi + 2) / 2 <= tl) bi++;
+  while (bi * (bi + 1) / 2 > tl) bi--;
+  const int bj = tl - bi * (bi + 1) / 2;
+  const int ia = f.ns + bi * TB, ie = min(ia + TB, f.nf);
+  const int ja = f.ns + bj * TB, je = min(ja + TB, f.nf);
+  const int K = f.ns;
+  const bool tri = bi == bj;
+  T* Cb = f.Ub + (ia - f.ns) + (int64_t)(ja - f.ns) * f.nu;
+  const int64_t ldc = f.nu;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;   // the wave's 64 x 64 sub-tile
+  const int il = lane & 15;
+  typename MF<T>::acc acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = MF<T>::zero();
+  // staging: a chunk column of 128 rows is TB * sizeof(T) / 256 load instructions
+  // of 4-byte pieces (lane l: piece l % EPL of row h * RPI + l / EPL); rows past the
+  // tile are clamped (they feed outputs that are not written), columns past the
+  // depth clamped and then zeroed in LDS
+  constexpr int EPL = sizeof(T) / 4;        // 4-byte pieces per element
+  constexpr int RPI = 64 / EPL;             // rows per load instruction
+  constexpr int IPC = TB / RPI;             // load instructions per column
+  constexpr int IPW = KC * IPC / (NT / 64); // load instructions per operand and wave
+  constexpr int W1 = 2 * IPW;               // one chunk's loads per wave (A and B)
+  static_assert(NT == 256, "four waves");
+  static_assert(W1 * (NS - 2) <= 63, "vmcnt range");
+  const int nch = (K + KC - 1) / KC;
+  auto issue = [&](int ch, T* Ab, T* Bb) {
+    const int q0 = ch * KC;
+#pragma unroll
+    for (int u = 0; u < IPW; u++) {
+      const int idx = wave * IPW + u, c = idx / IPC, h = idx % IPC;
+      const int64_t q = min(q0 + c, K - 1);
+      const int row = h * RPI + lane / EPL;
+      const char* sa = reinterpret_cast<const char*>(Lp + min(ia + row, ie - 1) + q * f.nf) + 4 * (lane % EPL);
+      const char* sb = reinterpret_cast<const char*>(Wp + min(ja + row, je - 1) + q * f.nf) + 4 * (lane % EPL);
+      __builtin_amdgcn_global_load_lds(sa, (__attribute__((address_space(3))) void*)(Ab + c * CS + h * RPI), 4, 0, 0);
+      __builtin_amdgcn_global_load_lds(sb, (__attribute__((address_space(3))) void*)(Bb + c * CS + h * RPI), 4, 0, 0);
+    }
+  };
+  const int m = lane & 15, kk = lane >> 4;
+  const uint32_t offA = ((wr + m) + kk * CS) * (uint32_t)sizeof(T);
+  const uint32_t offB = ((wc + m) + kk * CS) * (uint32_t)sizeof(T);
+  auto mult = [&](const T* Ab, const T* Bb) {
+    typedef __attribute__((address_space(3))) T* lds_ptr;   // 32-bit LDS addresses
+    const uint32_t ba = (uint32_t)(uintptr_t)(lds_ptr)Ab + offA;
+    const uint32_t bb = (uint32_t)(uintptr_t)(lds_ptr)Bb + offB;
+    T av[2][4], bv[2][4];
+    lds_read_cb128(ba, bb, av, bv);
+#pragma unroll
+    for (int s2 = 0; s2 < 2; s2++)
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = MF<T>::step(bv[s2][b], av[s2][a], acc[a][b]);
+  };
+  auto zero_tail = [&](int ch, T* Ab, T* Bb) {
+    const int cv = K - ch * KC;
+    if (cv >= KC) return;
+    __syncthreads();
+    for (int x = tid; x < CS * KC; x += NT)
+      if (x / CS >= cv) { Ab[x] = 0.0; Bb[x] = 0.0; }
+    __syncthreads();
+  };
+#pragma unroll
+  for (int v = 0; v < NS - 1; v++)
+    if (v < nch) issue(v, As[v], Bs[v]);
+  for (int ch = 0; ch < nch; ch += NS) {
+#pragma unroll
+    for (int v = 0; v < NS; v++) {
+      const int c = ch + v;
+      if (c >= nch) break;
+      // chunk c has landed in this wave's pieces (up to NS - 2 later chunks may be
+      // in flight); after the barrier every wave's pieces have, and every wave is
+      // done with chunk c - 1, whose buffers chunk c + NS - 1 refills
+      const int later = min(NS - 2, nch - 1 - c);
+      if (later >= 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * W1));
+      else if (later == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(W1));
+      else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      if (c == nch - 1) zero_tail(c, As[v], Bs[v]);
+      if (c + NS - 1 < nch) issue(c + NS - 1, As[(v + NS - 1) % NS], Bs[(v + NS - 1) % NS]);
+      mult(As[v], Bs[v]);
+    }
+  }
+  // C -= product
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      T cv[4];
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
+        const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || i >= j);
+        cv[r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
+        const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || i >= j);
+        if (ok) Cb[i + (int64_t)j * ldc] = cv[r] - acc[a][b][r];
+      }
+    }
+}
+
 __global__ void k_set_scalar(double* p, double v) {
   if (threadIdx.x == 0) *p = v;
 }
@@ -1238,6 +1421,13 @@ void launch_gemm_lt(const FrontMeta& M, const Int2* tasks, int32_t count, int32_
 }
 
 template <typename T>
+void launch_gemm_cb128(const FrontMeta& M, const Int2* tasks, int32_t count, const Batch& bt, int nb,
+                       T* L, T* U, const T* W, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL((k_gemm_cb128<256, T>), dim3(count, nb), dim3(256), 0, s, M, tasks, bt, L, U, W);
+}
+
+template <typename T>
 void launch_gemm_reduce(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int nseg,
                         const Batch& bt, int nb, T* L, const T* part, hipStream_t s) {
   if (count <= 0 || nseg <= 1) return;
@@ -1259,6 +1449,8 @@ void launch_gemm_reduce(const FrontMeta& M, const Int2* tasks, int32_t count, in
                                      const T*, FactStats*, hipStream_t);                            \
   template void launch_gemm_lt<T>(const FrontMeta&, const Int2*, int32_t, int32_t, int, int, int,    \
                                   const Batch&, int, T*, T*, const T*, T*, hipStream_t);            \
+  template void launch_gemm_cb128<T>(const FrontMeta&, const Int2*, int32_t, const Batch&, int, T*,  \
+                                     T*, const T*, hipStream_t);                                   \
   template void launch_gemm_reduce<T>(const FrontMeta&, const Int2*, int32_t, int32_t, int,         \
                                       const Batch&, int, T*, const T*, hipStream_t);
 KTH_INSTANTIATE_FACTOR(double)
