@@ -44,8 +44,10 @@ constexpr int kAsmCols = 16;
 constexpr int kTrsmRows = 64;
 // Rows per gather task of the large-front solve.
 constexpr int kSolveChunk = 256;
-// rows below a pivot tile per workgroup of a large-front solve step
-constexpr int kSolveRows = 256;
+// solve: rows below a front's pivot block (L21) per task, and the forward pass's
+// column segment width there
+constexpr int kL21Rows = 256;
+constexpr int kL21Cols = 256;
 // Schur-update output tile.
 constexpr int kTile = 64;
 // fronts whose contribution block has at least this many rows update it on

@@ -241,8 +241,8 @@ static void build_schedule(Pencil& P) {
     }
     lp.cb128_cnt = (int32_t)((sched.size() - lp.cb128_off) / 2);
   }
-  std::vector<int64_t> pbase(S.nsup, -1);
-  P.splan.partial_half = 0;
+  std::vector<int32_t> l21base(S.nsup, 0);
+  int64_t l21_part = 0;
   // solve plan: small fronts reuse the factorization lists; large fronts get
   // gather tasks of kSolveChunk rows and reuse the panel tasks of each step
   P.splan.levels.assign(S.nlevels, SolveLevel());
@@ -264,37 +264,57 @@ static void build_schedule(Pencil& P) {
       SolveStep ss;
       ss.t = sp.t;
       ss.nfronts = sp.nfronts;
+      const int64_t k0 = sp.t * (int64_t)kNB;
+      // forward: rows below the tile inside the pivot block only (the rows below
+      // the block take the level's L21 launches)
       align2();
-      ss.task_off = (int32_t)sched.size();
+      ss.fwd_off = (int32_t)sched.size();
       for (int32_t q = 0; q < sp.nfronts; q++) {
         const int32_t s = sched[lp.large_off + q];
-        const int64_t ns = S.ns(s), nf = S.nf(s);
-        const int64_t rb = std::min<int64_t>(sp.t * (int64_t)kNB + kNB, ns);
-        if (rb >= nf) { sched.push_back(s); sched.push_back((int32_t)nf); }
-        for (int64_t r = rb; r < nf; r += kSolveRows) { sched.push_back(s); sched.push_back((int32_t)r); }
+        const int64_t ns = S.ns(s);
+        const int64_t rb = std::min<int64_t>(k0 + kNB, ns);
+        if (rb >= ns) { sched.push_back(s); sched.push_back((int32_t)ns); }
+        for (int64_t r = rb; r < ns; r += kNB) { sched.push_back(s); sched.push_back((int32_t)r); }
       }
-      ss.task_cnt = (int32_t)((sched.size() - ss.task_off) / 2);
+      ss.fwd_cnt = (int32_t)((sched.size() - ss.fwd_off) / 2);
+      // backward: the pivot-block columns before the tile, 64 at a time
+      align2();
+      ss.bwd_off = (int32_t)sched.size();
+      for (int32_t q = 0; q < sp.nfronts; q++) {
+        const int32_t s = sched[lp.large_off + q];
+        if (k0 == 0) { sched.push_back(s); sched.push_back(0); }
+        for (int64_t c = 0; c < k0; c += kNB) { sched.push_back(s); sched.push_back((int32_t)c); }
+      }
+      ss.bwd_cnt = (int32_t)((sched.size() - ss.bwd_off) / 2);
       sl.steps.push_back(ss);
     }
-    // backward partial-sum slots: front s owns as many as its step-0 row chunks
-    int64_t slots = 0;
+    // L21 tasks: kL21Rows-row chunks of the rows below each pivot block
+    align2();
+    sl.l21_off = (int32_t)sched.size();
     for (int32_t q = 0; q < lp.large_cnt; q++) {
       const int32_t s = sched[lp.large_off + q];
-      const int64_t ns = S.ns(s), nf = S.nf(s), rb = std::min<int64_t>(kNB, ns);
-      pbase[s] = slots;
-      slots += nf > rb ? (nf - rb + kSolveRows - 1) / kSolveRows : 1;
+      const int64_t ns = S.ns(s), nf = S.nf(s);
+      l21base[s] = (int32_t)((sched.size() - sl.l21_off) / 2);
+      if (nf <= ns) continue;
+      sl.l21_nseg = std::max<int32_t>(sl.l21_nseg, (int32_t)((ns + kL21Cols - 1) / kL21Cols));
+      sl.l21_ntile = std::max<int32_t>(sl.l21_ntile, (int32_t)((ns + kNB - 1) / kNB));
+      for (int64_t r = ns; r < nf; r += kL21Rows) { sched.push_back(s); sched.push_back((int32_t)r); }
     }
-    P.splan.partial_half = std::max(P.splan.partial_half, slots);
+    sl.l21_cnt = (int32_t)((sched.size() - sl.l21_off) / 2);
+    l21_part = std::max<int64_t>(l21_part, (int64_t)sl.l21_cnt *
+                                               std::max<int64_t>((int64_t)sl.l21_nseg * kL21Rows,
+                                                                 (int64_t)sl.l21_ntile * kNB));
   }
-  P.splan.partial_size = std::max<int64_t>(1, 2 * P.splan.partial_half * kNB);
+  P.splan.l21_part_off = 0;
+  P.splan.partial_size = std::max<int64_t>(1, l21_part);
   Ctx* c = P.ctx;
   P.d_sched.upload(c, sched);
   P.h_sched = sched;
   P.d_tptr.upload(c, tptr);
   P.d_tilew.upload(c, tilew);
-  P.d_pbase.upload(c, pbase);
+  P.d_l21base.upload(c, l21base);
   P.splan.sched = P.d_sched.get();
-  P.splan.pbase = P.d_pbase.get();
+  P.splan.l21base = P.d_l21base.get();
 }
 
 // Rows of one CSR pattern: in range, strictly increasing columns.

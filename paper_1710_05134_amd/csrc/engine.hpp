@@ -139,8 +139,8 @@ struct Pencil {
   DBuf<double> aval, bval, zeros;
   // device metadata
   DBuf<int64_t> d_sfirst, d_rptr, d_lptr, d_uptr, d_tptr, d_eptr, d_cptr, d_acptr, d_asrc,
-      d_adst, d_perm, d_pbase;
-  DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched, d_imap;
+      d_adst, d_perm;
+  DBuf<int32_t> d_rows, d_emap, d_clist, d_tilew, d_sched, d_imap, d_l21base;
   DBuf<int64_t> d_iptr;
   FrontMeta meta{};
   std::vector<LevelPlan> levels;

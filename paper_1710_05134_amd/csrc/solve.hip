@@ -5,6 +5,10 @@
 // tails of their work vectors) and hands its own tail to its parent, so no two
 // fronts ever write the same entry.  Tile permutations are applied when the
 // solve reaches each tile (the factor keeps earlier panels' rows unswapped).
+// For a large front the chain of tile steps touches only its pivot block L11;
+// the rows below it (L21, most of the factor) take two wide launches per level
+// and pass: forward r2 -= L21 z, backward y1 -= L21^T x2, each as partial sums
+// over fixed pieces added in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -218,21 +222,22 @@ __device__ inline void wave_column_sums(double (&v)[kNB], int lane) {
   column_sums_step<kNB / 2>(v, lane);
 }
 
-constexpr int kFwdThreads = 64 + kSolveRows;   // wave 0: tile solve; the rest: one row each
-constexpr int kBwdThreads = kSolveRows;        // one row each (four waves)
+constexpr int kChainBlk = 64;                      // rows / columns of a chain-step task
+constexpr int kChainThreads = 64 + 4 * kChainBlk;  // wave 0: the tile; then four threads per row
 
 // Forward tile step t of the large fronts of a level, one launch.  Every
 // workgroup solves L_tt z = P_t r_t itself (wave 0, the 64x64 tile in registers,
-// row = lane) while its other waves load their rows' 64 entries of L below the
-// tile; then R_i -= L(i, tile) z for its kSolveRows rows.  The workgroup of a
-// front's first row chunk also writes y = D^{-1} z.  A front without rows below
-// the tile has one task with an empty row range.
+// row = lane) while its other threads load their share of the kChainBlk rows of
+// the pivot block below the tile (four threads per row, 16 columns each); then
+// R_i -= L(i, tile) z.  The workgroup of a front's first row chunk also writes
+// y = D^{-1} z, and z itself for the rows below the pivot block.  A front without
+// pivot-block rows below the tile has one task with an empty row range.
 template <typename T>
-__global__ __launch_bounds__(kFwdThreads) void k_lfwd_step(FrontMeta M, const Int2* tasks, int t,
-                                                           const T* L, const double* __restrict__ D,
-                                                           const double* __restrict__ E,
-                                                           const int32_t* __restrict__ tperm,
-                                                           double* R, double* ye) {
+__global__ __launch_bounds__(kChainThreads) void k_lfwd_step(FrontMeta M, const Int2* tasks, int t,
+                                                             const T* L, const double* __restrict__ D,
+                                                             const double* __restrict__ E,
+                                                             const int32_t* __restrict__ tperm,
+                                                             double* R, double* ye, double* xe) {
   __shared__ double z[kNB];
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, r0 = tk.b;
@@ -243,12 +248,15 @@ __global__ __launch_bounds__(kFwdThreads) void k_lfwd_step(FrontMeta M, const In
   const int k0 = t * kNB, kb = min(kNB, ns - k0);
   const T* Lp = L + M.lptr[s];
   double* Rs = R + M.rptr[s];
-  double Lv[kNB];
-  const int i = r0 + tid - 64;
+  const int u = tid - 64, qr = u & 3;
+  const int i = r0 + (u >> 2);
+  double v[16];
+  double ri = 0.0;
   // unconditional loads from clamped (valid) addresses, masked afterwards, so that
-  // all 64 are in flight together
+  // they are all in flight together
   if (tid < 64) {
     const int lc = min(lane, kb - 1);
+    double Lv[kNB];
 #pragma unroll
     for (int p = 0; p < kNB; p++) Lv[p] = (double)Lp[(k0 + lc) + (int64_t)(k0 + min(p, kb - 1)) * nf];
     // strictly lower part of the tile only, so that every step updates all lanes
@@ -257,139 +265,203 @@ __global__ __launch_bounds__(kFwdThreads) void k_lfwd_step(FrontMeta M, const In
     double zl = lane < kb ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
 #pragma unroll
     for (int p = 0; p < kNB; p++) zl = fma(-Lv[p], lane_value(zl, p), zl);
-    z[lane] = zl;
+    z[lane] = zl;   // zero beyond kb
   } else {
-    const int ic = min(i, nf - 1);
+    const int ic = min(i, ns - 1);
 #pragma unroll
-    for (int q = 0; q < kNB; q++) Lv[q] = (double)Lp[ic + (int64_t)(k0 + min(q, kb - 1)) * nf];
-#pragma unroll
-    for (int q = 0; q < kNB; q++) Lv[q] = q < kb ? Lv[q] : 0.0;
+    for (int c = 0; c < 16; c++) v[c] = (double)Lp[ic + (int64_t)(k0 + min(qr * 16 + c, kb - 1)) * nf];
+    // this row's right-hand side, read before the barrier: rows below the tile are
+    // written by their own workgroup only
+    if (qr == 0 && i < ns) ri = Rs[i];
   }
-  // this row's right-hand side, read before the barrier: rows below the tile are
-  // written by their own workgroup only
-  const double ri = (tid >= 64 && i < nf) ? Rs[i] : 0.0;
   __syncthreads();
-  if (tid >= 64 && i < nf) {
+  if (tid >= 64) {
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < kNB; q++) acc = fma(Lv[q], z[q], acc);
-    Rs[i] = ri - acc;
+    for (int c = 0; c < 16; c++) acc = fma(v[c], z[qr * 16 + c], acc);
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (qr == 0 && i < ns) Rs[i] = ri - acc;
   }
-  if (r0 == k0 + kb && tid < kb) ye[f0 + k0 + tid] = apply_dinv(D, E, z, f0 + k0 + tid, tid, kb);
+  // the first chunk's workgroup: y = D^{-1} z, and z itself for the rows below the
+  // pivot block (xe of the pivots is free once the level's gather has read it)
+  if (r0 == k0 + kb && tid < kb) {
+    ye[f0 + k0 + tid] = apply_dinv(D, E, z, f0 + k0 + tid, tid, kb);
+    xe[f0 + k0 + tid] = z[tid];
+  }
 }
 
-// Backward, tile t of front s: w = L_tt^{-T} (y_t - sum of the front's partial
-// column sums of step t, in chunk order), x(f0 + k0 + perm[q]) = w_q.  Called by
-// all threads of a workgroup; tl: LDS staging of the tile (row-major, padded).
+// Forward, rows below the pivot block: workgroup (task, seg) stores for its
+// kL21Rows rows the products with column segment seg,
+//   P[(task nseg + seg) kL21Rows + r] = sum_{q in seg} L(r0 + r, q) z_q,
+// z_q = xe[f0 + q]; segments past the front's columns store nothing.
 template <typename T>
-__device__ inline void bwd_finish_tile(const FrontMeta& M, int s, int t, const T* L,
-                                       const int32_t* __restrict__ tperm,
-                                       const double* __restrict__ ye, const double* partial,
-                                       double* xe, double (&tl)[kNB][kNB + 1]) {
+__global__ __launch_bounds__(kL21Rows) void k_lfwd_l21(FrontMeta M, const Int2* tasks, int nseg,
+                                                       const T* L, const double* __restrict__ xe,
+                                                       double* P) {
+  __shared__ double z[kL21Cols];
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a, r0 = tk.b, seg = blockIdx.y;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int c0 = seg * kL21Cols;
+  if (c0 >= ns) return;
+  const int c1 = min(c0 + kL21Cols, ns);
+  const int tid = threadIdx.x;
+  for (int q = tid; q < c1 - c0; q += kL21Rows) z[q] = xe[f0 + c0 + q];
+  __syncthreads();
+  const int i = r0 + tid;
+  if (i >= nf) return;
+  const T* Lp = L + M.lptr[s] + i;
+  double acc = 0.0;
+  int q = c0;
+  for (; q + 8 <= c1; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = (double)Lp[(int64_t)(q + u) * nf];
+#pragma unroll
+    for (int u = 0; u < 8; u++) acc = fma(v[u], z[q - c0 + u], acc);
+  }
+  for (; q < c1; q++) acc = fma((double)Lp[(int64_t)q * nf], z[q - c0], acc);
+  P[((int64_t)blockIdx.x * nseg + seg) * kL21Rows + tid] = acc;
+}
+
+// R_i -= the segments' products of row i, in segment order.
+__global__ __launch_bounds__(kL21Rows) void k_lfwd_l21_reduce(FrontMeta M, const Int2* tasks,
+                                                              int nseg, const double* P, double* R) {
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a, r0 = tk.b;
+  const int ns = (int)(M.sfirst[s + 1] - M.sfirst[s]);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int i = r0 + (int)threadIdx.x;
+  if (i >= nf) return;
+  const int used = (ns + kL21Cols - 1) / kL21Cols;
+  const double* p = P + (int64_t)blockIdx.x * nseg * kL21Rows + threadIdx.x;
+  double sum = 0.0;
+  for (int g = 0; g < used; g++) sum += p[(int64_t)g * kL21Rows];
+  R[M.rptr[s] + i] -= sum;
+}
+
+// Backward tile step t (tiles in reverse), one launch, in the form that pushes each
+// finished tile into the columns before it.  Every workgroup solves L_tt^T w = y_t
+// itself (wave 0: the tile through LDS, column = lane), y_t having received the
+// contributions of all later tiles and of the rows below the pivot block; then its
+// other threads subtract, for kChainBlk columns j < k0 of the pivot block (four
+// threads per column, 16 tile rows each), y_j -= sum_i L(k0 + i, j) x_i, the rows
+// i of the tile in their stored (unswapped) order.  The workgroup of the first
+// column chunk writes x(f0 + k0 + perm[q]) = w_q.  Tile 0 has one task with an
+// empty column range.
+template <typename T>
+__global__ __launch_bounds__(kChainThreads) void k_lbwd_push(FrontMeta M, const Int2* tasks, int t,
+                                                             const T* L,
+                                                             const int32_t* __restrict__ tperm,
+                                                             double* ye, double* xe) {
+  __shared__ double tl[kNB][kNB + 1];
+  __shared__ double xs[kNB];
+  const Int2 tk = tasks[blockIdx.x];
+  const int s = tk.a, c0 = tk.b;
   const int tid = threadIdx.x, lane = tid & 63;
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
-  const int k0 = t * kNB, kb = min(kNB, ns - k0), rb = k0 + kb;
-  const int ntask = nf > rb ? (nf - rb + kSolveRows - 1) / kSolveRows : 1;
+  const int k0 = t * kNB, kb = min(kNB, ns - k0);
   const T* Lp = L + M.lptr[s];
-  for (int e = tid; e < kNB * kNB; e += blockDim.x) {
-    const int r = e & 63, c = e >> 6;
-    tl[r][c] = (r < kb && c < kb) ? (double)Lp[(k0 + r) + (int64_t)(k0 + c) * nf] : 0.0;
-  }
-  __syncthreads();
+  const int u = tid - 64, qr = u & 3;
+  const int j = c0 + (u >> 2);
+  double v[16];
   if (tid < 64) {
-    // partial sums in chunk order, loaded eight at a time
-    double acc = 0.0;
-    for (int j0 = 0; j0 < ntask; j0 += 8) {
-      double pv[8];
+    // row lane of the tile into LDS (coalesced loads), then column lane from it;
+    // one wave: its LDS writes and reads complete in order
+    const int lc = min(lane, kb - 1);
+    double Lr[kNB];
 #pragma unroll
-      for (int u = 0; u < 8; u++) pv[u] = partial[(int64_t)min(j0 + u, ntask - 1) * kNB + lane];
+    for (int p = 0; p < kNB; p++) Lr[p] = (double)Lp[(k0 + lc) + (int64_t)(k0 + min(p, kb - 1)) * nf];
+    double g = lane < kb ? ye[f0 + k0 + lane] : 0.0;
+    const int tp = lane < kb ? tperm[f0 + k0 + lane] : 0;
 #pragma unroll
-      for (int u = 0; u < 8; u++)
-        if (j0 + u < ntask) acc += pv[u];
-    }
-    double g = lane < kb ? ye[f0 + k0 + lane] - acc : 0.0;
-    // column lane of the tile, strictly below the diagonal
+    for (int p = 0; p < kNB; p++) tl[lane][p] = Lr[p];
     double Lc[kNB];
 #pragma unroll
-    for (int p = 0; p < kNB; p++) Lc[p] = p > lane ? tl[p][lane] : 0.0;
+    for (int p = 0; p < kNB; p++) Lc[p] = (p > lane && p < kb) ? tl[p][lane] : 0.0;
+    // w_q = g_q - sum_{p > q} L(p, q) w_p, p descending (zero beyond kb)
 #pragma unroll
     for (int p = kNB - 1; p >= 0; p--) g = fma(-Lc[p], lane_value(g, p), g);
-    if (lane < kb) xe[f0 + k0 + tperm[f0 + k0 + lane]] = g;
+    xs[lane] = 0.0;
+    if (lane < kb) xs[tp] = g;
+    if (c0 == 0 && lane < kb) xe[f0 + k0 + tp] = g;
+  } else {
+    const int jc = min(j, max(k0 - 1, 0));
+#pragma unroll
+    for (int c = 0; c < 16; c++) v[c] = (double)Lp[(k0 + min(qr * 16 + c, kb - 1)) + (int64_t)jc * nf];
   }
   __syncthreads();
+  if (tid >= 64) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; c++) acc = fma(v[c], xs[qr * 16 + c], acc);
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (qr == 0 && j < k0) ye[f0 + j] -= acc;
+  }
 }
 
-// Backward tile step t (tiles in reverse), one launch, no inter-workgroup
-// synchronisation: the workgroup of a front's first row chunk first finishes tile
-// t+1 (whose rows open its chunk) from the partial sums the previous launch left;
-// then every workgroup stores the column sums sum_i L(i, k0+q) x(rows[i]) of its
-// kSolveRows rows (row = thread, coalesced loads, wave_column_sums) in the front's
-// slot for this step's parity.  Tile 0 is finished by k_lbwd_finish.
-// partial: [2][slots][kNB]; pbase[s]: the front's first slot (its chunk j at +j).
+// Backward, rows below the pivot block: workgroup (task, t) stores the column sums
+// of its kL21Rows rows over pivot tile t,
+//   P[(task ntile + t) kNB + q] = sum_i L(i, k0 + q) x(rows[i]),
+// row = thread (coalesced loads), wave_column_sums; tiles past the front's columns
+// store nothing.
 template <typename T>
-__global__ __launch_bounds__(kBwdThreads) void k_lbwd_step(FrontMeta M, const Int2* tasks, int t,
-                                                           const T* L,
-                                                           const int32_t* __restrict__ tperm,
-                                                           const double* __restrict__ ye,
-                                                           const int64_t* __restrict__ pbase,
-                                                           int64_t half, double* partial,
-                                                           double* xe) {
-  __shared__ double wsum[kBwdThreads / 64][kNB];
-  __shared__ double tl[kNB][kNB + 1];
+__global__ __launch_bounds__(kL21Rows) void k_lbwd_l21(FrontMeta M, const Int2* tasks, int ntile,
+                                                       const T* L, const double* __restrict__ xe,
+                                                       double* P) {
+  __shared__ double wsum[kL21Rows / 64][kNB];
   const Int2 tk = tasks[blockIdx.x];
-  const int s = tk.a, r0 = tk.b;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = tk.a, r0 = tk.b, t = blockIdx.y;
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
-  const int k0 = t * kNB, kb = min(kNB, ns - k0);
-  const int rb = k0 + kb;                      // first row below the tile
-  const int64_t pb = pbase[s];
+  const int k0 = t * kNB;
+  if (k0 >= ns) return;
+  const int kb = min(kNB, ns - k0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = r0 + tid;
   const int ic = min(i, nf - 1);
-  const int64_t gi = M.rows[M.rptr[s] + ic];
-  // tile t+1 exists and opens this chunk: this workgroup finishes it first; x of
-  // its rows is ready after that, x of every other row already
-  const bool fin = r0 == rb && rb < ns;
-  const bool late = fin && i < min(rb + kNB, ns);
-  double xi = (!late && i < nf) ? xe[gi] : 0.0;
-  if (fin) bwd_finish_tile(M, s, t + 1, L, tperm, ye, partial + (((t + 1) & 1) * half + pb) * kNB, xe, tl);
-  if (late) xi = xe[gi];
+  const double xi = i < nf ? xe[M.rows[M.rptr[s] + ic]] : 0.0;
   const T* Lp = L + M.lptr[s];
-  {
-    // unconditional loads from clamped (valid) addresses, masked afterwards, so
-    // that all 64 are in flight together
-    double v[kNB];
+  double v[kNB];
 #pragma unroll
-    for (int q = 0; q < kNB; q++) v[q] = (double)Lp[ic + (int64_t)(k0 + min(q, kb - 1)) * nf];
+  for (int q = 0; q < kNB; q++) v[q] = (double)Lp[ic + (int64_t)(k0 + min(q, kb - 1)) * nf];
 #pragma unroll
-    for (int q = 0; q < kNB; q++) v[q] = q < kb ? v[q] * xi : 0.0;
-    wave_column_sums(v, lane);
-    wsum[wave][lane] = v[0];
-  }
+  for (int q = 0; q < kNB; q++) v[q] = q < kb ? v[q] * xi : 0.0;
+  wave_column_sums(v, lane);
+  wsum[wave][lane] = v[0];
   __syncthreads();
   if (tid < 64) {
     double acc = 0.0;
 #pragma unroll
-    for (int w = 0; w < kBwdThreads / 64; w++) acc += wsum[w][lane];
-    const int j = (r0 - rb) / kSolveRows;
-    partial[((t & 1) * half + pb + j) * kNB + lane] = acc;
+    for (int w = 0; w < kL21Rows / 64; w++) acc += wsum[w][lane];
+    P[((int64_t)blockIdx.x * ntile + t) * kNB + lane] = acc;
   }
 }
 
-// Backward: tile 0 of every large front of a level (one workgroup per front).
-template <typename T>
-__global__ __launch_bounds__(kBwdThreads) void k_lbwd_finish(FrontMeta M, const int32_t* fronts,
-                                                             const T* L,
-                                                             const int32_t* __restrict__ tperm,
-                                                             const double* __restrict__ ye,
-                                                             const int64_t* __restrict__ pbase,
-                                                             const double* partial, double* xe) {
-  __shared__ double tl[kNB][kNB + 1];
-  const int s = fronts[blockIdx.x];
-  bwd_finish_tile(M, s, 0, L, tperm, ye, partial + pbase[s] * kNB, xe, tl);
+// y(f0 + k0 + q) -= the row chunks' column sums of tile t, in chunk order
+// (workgroup (front, t), one lane per column).
+__global__ __launch_bounds__(64) void k_lbwd_l21_reduce(FrontMeta M, const int32_t* fronts,
+                                                        const int32_t* __restrict__ l21base,
+                                                        int ntile, const double* P, double* ye) {
+  const int s = fronts[blockIdx.x], t = blockIdx.y, lane = threadIdx.x;
+  const int64_t f0 = M.sfirst[s];
+  const int ns = (int)(M.sfirst[s + 1] - f0);
+  const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
+  const int k0 = t * kNB;
+  if (k0 >= ns || nf <= ns) return;
+  const int kb = min(kNB, ns - k0);
+  const int nrb = (nf - ns + kL21Rows - 1) / kL21Rows;
+  const double* p = P + ((int64_t)l21base[s] * ntile + t) * kNB + lane;
+  double sum = 0.0;
+  for (int j = 0; j < nrb; j++) sum += p[(int64_t)j * ntile * kNB];
+  if (lane < kb) ye[f0 + k0 + lane] -= sum;
 }
 
 __global__ void k_gather(int64_t n, const int64_t* __restrict__ perm, const double* __restrict__ x,
@@ -419,6 +491,7 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
                    const double* b, double* x, double* xe, double* ye, double* R, double* partial,
                    hipStream_t s) {
   const int32_t* sc = P.sched;
+  double* p21 = partial + P.l21_part_off;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(256), 0, s, n, perm, b, xe);
   for (const SolveLevel& lv : P.levels) {
     if (lv.small_cnt > 0)
@@ -428,23 +501,34 @@ void solve_enqueue(const SolvePlan& P, const FrontMeta& M, const T* L, const dou
     hipLaunchKernelGGL((k_lfwd_init<T>), dim3(lv.init_cnt), dim3(NT), 0, s, M,
                        reinterpret_cast<const Int2*>(sc + lv.init_off), xe, R);
     for (const SolveStep& st : lv.steps)
-      hipLaunchKernelGGL((k_lfwd_step<T>), dim3(st.task_cnt), dim3(kFwdThreads), 0, s, M,
-                         reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, D, E, tperm, R, ye);
+      hipLaunchKernelGGL((k_lfwd_step<T>), dim3(st.fwd_cnt), dim3(kChainThreads), 0, s, M,
+                         reinterpret_cast<const Int2*>(sc + st.fwd_off), st.t, L, D, E, tperm, R, ye,
+                         xe);
+    if (lv.l21_cnt > 0) {
+      const Int2* tk = reinterpret_cast<const Int2*>(sc + lv.l21_off);
+      hipLaunchKernelGGL((k_lfwd_l21<T>), dim3(lv.l21_cnt, lv.l21_nseg), dim3(kL21Rows), 0, s, M, tk,
+                         lv.l21_nseg, L, xe, p21);
+      hipLaunchKernelGGL(k_lfwd_l21_reduce, dim3(lv.l21_cnt), dim3(kL21Rows), 0, s, M, tk,
+                         lv.l21_nseg, p21, R);
+    }
   }
   for (size_t l = P.levels.size(); l-- > 0;) {
     const SolveLevel& lv = P.levels[l];
     if (lv.small_cnt > 0)
       hipLaunchKernelGGL((k_solve_bwd<T>), dim3(lv.small_cnt), dim3(NT), 0, s, M, sc + lv.small_off,
                          L, tperm, ye, xe);
+    if (lv.l21_cnt > 0) {
+      const Int2* tk = reinterpret_cast<const Int2*>(sc + lv.l21_off);
+      hipLaunchKernelGGL((k_lbwd_l21<T>), dim3(lv.l21_cnt, lv.l21_ntile), dim3(kL21Rows), 0, s, M, tk,
+                         lv.l21_ntile, L, xe, p21);
+      hipLaunchKernelGGL(k_lbwd_l21_reduce, dim3(lv.large_cnt, lv.l21_ntile), dim3(64), 0, s, M,
+                         sc + lv.large_off, P.l21base, lv.l21_ntile, p21, ye);
+    }
     for (size_t q = lv.steps.size(); q-- > 0;) {
       const SolveStep& st = lv.steps[q];
-      hipLaunchKernelGGL((k_lbwd_step<T>), dim3(st.task_cnt), dim3(kBwdThreads), 0, s, M,
-                         reinterpret_cast<const Int2*>(sc + st.task_off), st.t, L, tperm, ye,
-                         P.pbase, P.partial_half, partial, xe);
+      hipLaunchKernelGGL((k_lbwd_push<T>), dim3(st.bwd_cnt), dim3(kChainThreads), 0, s, M,
+                         reinterpret_cast<const Int2*>(sc + st.bwd_off), st.t, L, tperm, ye, xe);
     }
-    if (lv.large_cnt > 0)
-      hipLaunchKernelGGL((k_lbwd_finish<T>), dim3(lv.large_cnt), dim3(kBwdThreads), 0, s, M,
-                         sc + lv.large_off, L, tperm, ye, P.pbase, partial, xe);
   }
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, s, n, perm, xe, x);
 }

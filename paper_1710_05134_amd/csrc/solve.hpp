@@ -12,8 +12,10 @@ namespace kth {
 struct SolveStep {
   int32_t t;
   int32_t nfronts;               // active large fronts (prefix of the level's list)
-  int32_t task_off, task_cnt;    // Int2 (front, first row) tasks of kSolveRows rows below the
-                                 // tile, in row order per front; (front, nf) if none
+  int32_t fwd_off, fwd_cnt;      // Int2 (front, first row) tasks of 64 pivot-block rows below
+                                 // the tile, in row order per front; (front, ns) if none
+  int32_t bwd_off, bwd_cnt;      // Int2 (front, first column) tasks of 64 columns before the
+                                 // tile, first chunk first; (front, 0) for tile 0
 };
 
 struct SolveLevel {
@@ -21,14 +23,19 @@ struct SolveLevel {
   int32_t large_off = 0, large_cnt = 0;   // large fronts (sorted by ns, descending)
   int32_t init_off = 0, init_cnt = 0;     // Int2 (front, row) tasks of the gather step
   std::vector<SolveStep> steps;
+  // rows below each large front's pivot block (L21): Int2 (front, first row) tasks of
+  // kL21Rows rows, in row order per front; the forward pass splits the columns into
+  // l21_nseg segments of kL21Cols, the backward pass into l21_ntile tiles of kNB
+  int32_t l21_off = 0, l21_cnt = 0;
+  int32_t l21_nseg = 0, l21_ntile = 0;
 };
 
 struct SolvePlan {
   const int32_t* sched = nullptr;    // device int32 schedule array
   std::vector<SolveLevel> levels;
-  int64_t partial_size = 1;          // doubles for the backward partial sums: 2 * half * kNB
-  int64_t partial_half = 0;          // slots per step parity (max over levels)
-  const int64_t* pbase = nullptr;    // device [nsup]: a large front's first slot in its level
+  int64_t partial_size = 1;          // doubles for the L21 partial sums (max over levels)
+  const int32_t* l21base = nullptr;  // device [nsup]: a large front's first L21 task in its level
+  int64_t l21_part_off = 0;          // doubles: the L21 partial sums' place within partial
 };
 
 // Size of the fixed per-GPU work array of the allocation-free solve.
