@@ -55,6 +55,8 @@ constexpr int kTile = 64;
 constexpr int kCb128MinNu = 384;
 // depth segment of a split left-looking update of the rows below a pivot tile
 constexpr int kSegK = 256;
+// workgroups a split-depth left-looking launch aims at (four per CU)
+constexpr int kLLTargetWgs = 1024;
 // the diagonal block's update (one output tile per front, on the critical path)
 // takes segments of at least kSegKDiag columns, at most kMaxSegDiag of them
 constexpr int kSegKDiag = 32;

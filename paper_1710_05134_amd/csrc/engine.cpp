@@ -133,9 +133,19 @@ static int64_t cb128_min_nu() {
   return v < 1 ? 1 : (int64_t)v;
 }
 
+// Workgroups a split-depth left-looking launch aims at (KTH_LL_WGS overrides,
+// read when a pencil is created).
+static int64_t ll_target_wgs() {
+  const char* e = std::getenv("KTH_LL_WGS");
+  if (!e || !*e) return kLLTargetWgs;
+  const long long v = std::atoll(e);
+  return v < 1 ? 1 : (int64_t)v;
+}
+
 static void build_schedule(Pencil& P) {
   const Symbolic& S = P.S;
   const int64_t nu_big = cb128_min_nu();
+  const int64_t ll_wgs = ll_target_wgs();
   P.cb128_min_nu = nu_big;
   std::vector<int32_t> sched;
   auto align2 = [&]() { if (sched.size() & 1) sched.push_back(0); };
@@ -167,7 +177,7 @@ static void build_schedule(Pencil& P) {
       sched.push_back(s);
       tilew[s] = kNB;
       tptr[s] = toff;
-      toff += kNB * kNB;
+      toff += 2 * kNB * kNB;   // tile inverses of even and odd steps
     }
     P.tsize = std::max(P.tsize, toff);
     align2();
@@ -184,16 +194,24 @@ static void build_schedule(Pencil& P) {
       while (act < (int32_t)large.size() && S.ns(large[act]) > t * kNB) act++;
       sp.nfronts = act;
       align2();
+      // panel solve: the first kTrsmRows rows below the tile (the next tile's rows,
+      // which the next diagonal-block update needs) apart from the rest
       sp.trsm_off = (int32_t)sched.size();
-      std::vector<int32_t> tpre(1, 0);
       for (int32_t q = 0; q < act; q++) {
         int32_t s = large[q];
         int64_t ns = S.ns(s), nf = S.nf(s);
         int64_t k0 = t * kNB, kb = std::min<int64_t>(kNB, ns - k0);
-        for (int64_t r = k0 + kb; r < nf; r += kTrsmRows) { sched.push_back(s); sched.push_back((int32_t)r); }
-        tpre.push_back((int32_t)((sched.size() - sp.trsm_off) / 2));
+        if (k0 + kb < nf) { sched.push_back(s); sched.push_back((int32_t)(k0 + kb)); }
       }
       sp.trsm_cnt = (int32_t)((sched.size() - sp.trsm_off) / 2);
+      sp.trsm2_off = (int32_t)sched.size();
+      for (int32_t q = 0; q < act; q++) {
+        int32_t s = large[q];
+        int64_t ns = S.ns(s), nf = S.nf(s);
+        int64_t k0 = t * kNB, kb = std::min<int64_t>(kNB, ns - k0);
+        for (int64_t r = k0 + kb + kTrsmRows; r < nf; r += kTrsmRows) { sched.push_back(s); sched.push_back((int32_t)r); }
+      }
+      sp.trsm2_cnt = (int32_t)((sched.size() - sp.trsm2_off) / 2);
       // left-looking update of this tile's column block (steps after the first):
       // its diagonal block, then rows below it in kTile chunks
       sp.ll_diag_off = (int32_t)sched.size();
@@ -212,7 +230,16 @@ static void build_schedule(Pencil& P) {
       // kSegKDiag deep and at most kMaxSegDiag of them (the ordered reduction
       // reads each)
       const int64_t depth = (int64_t)t * kNB;
-      sp.ll_nseg = std::max<int32_t>(1, (int32_t)((depth + kSegK - 1) / kSegK));
+      // rows below: as many segments (each at least kSegK deep, a multiple of 16) as
+      // bring the launch to about ll_wgs workgroups
+      {
+        const int64_t most = std::max<int64_t>(1, (depth + kSegK - 1) / kSegK);
+        const int64_t want = (ll_wgs + std::max<int64_t>(sp.ll_rest_cnt, 1) - 1) /
+                             std::max<int64_t>(sp.ll_rest_cnt, 1);
+        const int64_t ns_ = std::min(most, std::max<int64_t>(1, want));
+        sp.ll_segk = (int32_t)std::max<int64_t>(kSegK, ((depth + ns_ - 1) / ns_ + 15) / 16 * 16);
+        sp.ll_nseg = std::max<int32_t>(1, (int32_t)((depth + sp.ll_segk - 1) / sp.ll_segk));
+      }
       sp.ll_segk_d = (int32_t)std::max<int64_t>(
           kSegKDiag, ((depth + kMaxSegDiag - 1) / kMaxSegDiag + 15) / 16 * 16);
       sp.ll_nseg_d = std::max<int32_t>(1, (int32_t)((depth + sp.ll_segk_d - 1) / sp.ll_segk_d));
@@ -734,6 +761,15 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
                           sp.t, bt, nb, Lf, Wf, F.D.get(), F.E.get(), F.tperm.get(),
                           Tf, F.stats.get(), st);
       }
+      // the rest of the panel solve: after the next tile is handed to the second
+      // stream (it reads tile t's inverse from the slot of t's parity)
+      auto trsm_rest = [&]() {
+        ProfScope ps(prof, st, PROF_TRSM, 0.0);
+        launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm2_off), sp.trsm2_cnt,
+                          sp.t, bt, nb, Lf, Wf, F.D.get(), F.E.get(), F.tperm.get(),
+                          Tf, F.stats.get(), st);
+      };
+      if (q + 1 == lp.steps.size()) trsm_rest();
       if (q + 1 < lp.steps.size()) {
         const StepPlan& nx = lp.steps[q + 1];
         const StepCost cn = step_cost(nx);
@@ -756,9 +792,10 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
                              F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), c->aux);
         }
         KTH_HIP(hipEventRecord(c->ev_tile, c->aux));
+        trsm_rest();
         {
           ProfScope ps(prof, st, PROF_GEMM, cn.ll, cn.ll_bytes);
-          launch_gemm_lt(P.meta, rtask, nx.ll_rest_cnt, nx.t, 1, nx.ll_nseg, kSegK, bt, nb, Lf, Uf, Wf, Pf,
+          launch_gemm_lt(P.meta, rtask, nx.ll_rest_cnt, nx.t, 1, nx.ll_nseg, nx.ll_segk, bt, nb, Lf, Uf, Wf, Pf,
                          st);
         }
         if (nx.ll_nseg > 1 && nx.ll_rest_cnt > 0) {

@@ -738,7 +738,8 @@ __global__ __launch_bounds__(NT) void k_tile_factor(FrontMeta M, const int32_t* 
     }
   }
   __syncthreads();
-  T* Ti = tinv + M.tptr[s];
+  T* Ti = tinv + M.tptr[s] + (t & 1) * (kNB * kNB);   // two slots: tile t+1 may be factored
+                                                      // while tile t's panel solve runs
   for (int x0 = 0; x0 < kNB * kNB; x0 += NT * U) {
     T v[U];
 #pragma unroll
@@ -859,7 +860,7 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
   const int kb = min(kNB, ns - k0);
   T* Lp = L + M.lptr[s];
   T* Wp = W + M.lptr[s];   // W = L D, panel-shaped
-  const T* Ti = tinv + M.tptr[s];
+  const T* Ti = tinv + M.tptr[s] + (t & 1) * (kNB * kNB);
   for (int q = tid; q < kNB; q += NT) {
     dd[q] = q < kb ? D[f0 + k0 + q] : 1.0;
     ee[q] = q < kb ? E[f0 + k0 + q] : 0.0;
