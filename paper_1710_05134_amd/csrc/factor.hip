@@ -61,6 +61,22 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v) {
   return ab > cd ? ab : cd;
 }
 
+// Maximum of v over the 64 lanes, returned to every lane (the same DPP steps on
+// 32 bits).
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  unsigned o;
+  o = (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false); v = o > v ? o : v;
+  o = (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false); v = o > v ? o : v;
+  o = (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false); v = o > v ? o : v;
+  o = (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false); v = o > v ? o : v;
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  const unsigned ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
 // Value of v in lane p (p uniform) through v_readlane.
 __device__ inline double lane_value(double v, int p) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), p);
@@ -349,9 +365,8 @@ __device__ inline void tile_sym_swap(T* F, T* Lo, int ld, int kb, int k, int a, 
 // wave-uniform index is read through indirect register addressing.
 template <typename T> struct RowRegs { typedef T type __attribute__((ext_vector_type(kNB / 4))); };
 
-// Columns k and k + 1 of the registers, published by the waves that own them:
-// yb[0][i] = F(i, k) for k < i < kb, yb[1][i] = F(i, k + 1) for k + 1 < i < kb (zero
-// elsewhere); pv = F(k, k), F(k + 1, k), F(k + 1, k + 1).
+// Column k of the registers, published by the wave that owns it: yb[0][i] = F(i, k)
+// for k < i < kb (zero elsewhere); pv[0] = F(k, k), pv[1] = F(k + 1, k).
 template <typename T>
 __device__ __forceinline__ void bk_publish(const typename RowRegs<T>::type& R, T (&yb)[2][kNB],
                                            T (&pv)[3], int k, int kb, int wave, int i) {
@@ -361,6 +376,12 @@ __device__ __forceinline__ void bk_publish(const typename RowRegs<T>::type& R, T
     if (i == k) pv[0] = v;
     if (i == k + 1) pv[1] = v;
   }
+}
+// Column k + 1 (for a 2x2 pivot): yb[1][i] = F(i, k + 1) for k + 1 < i < kb (zero
+// elsewhere); pv[2] = F(k + 1, k + 1).
+template <typename T>
+__device__ __forceinline__ void bk_publish_next(const typename RowRegs<T>::type& R, T (&yb)[2][kNB],
+                                                T (&pv)[3], int k, int kb, int wave, int i) {
   if (k + 1 < kb && wave == ((k + 1) & 3)) {
     const T v = R[(k + 1) >> 2];
     yb[1][i] = (i > k + 1 && i < kb) ? v : (T)0.0;
@@ -389,11 +410,14 @@ __device__ void bk_tile_regs(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, B
     bk_publish<T>(R, yb[par], pv[par], k, kb, wave, i);
     __syncthreads();
     // gamma_1 and its row r among the candidates k < i < kb (ties: smallest row)
+    // (key: the upper 24 bits of |F(i, k)|, then 128 - i; rows whose magnitudes agree
+    // in exponent and the leading 12 mantissa bits count as ties)
     const T ck = yb[par][0][i];
-    unsigned long long key = 0;
-    if (i > k && i < kb) key = (dbits(fabs((double)ck)) & ~0xFFull) | (unsigned long long)(128 - i);
-    key = wave_max_u64(key);
-    const int r = key == 0 ? k : 128 - (int)(key & 0xFFull);
+    unsigned key = 0;
+    if (i > k && i < kb)
+      key = ((unsigned)(dbits(fabs((double)ck)) >> 32) & ~0xFFu) | (unsigned)(128 - i);
+    key = wave_max_u32(key);
+    const int r = key == 0 ? k : 128 - (int)(key & 0xFFu);
     const double g1 = key == 0 ? 0.0 : fabs((double)yb[par][0][r]);
     const double akk = fabs((double)pv[par][0]);
     int kind = 0;
@@ -418,8 +442,12 @@ __device__ void bk_tile_regs(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, B
 #pragma unroll
         for (int m = 0; m < NM; m++) R[m] = F[i + (4 * m + wave) * ld];
         bk_publish<T>(R, yb[par ^ 1], pv[par ^ 1], k, kb, wave, i);   // interchanged, other buffer
+        if (kind == 2) bk_publish_next<T>(R, yb[par ^ 1], pv[par ^ 1], k, kb, wave, i);
         __syncthreads();
         par ^= 1;
+      } else if (kind == 2) {
+        bk_publish_next<T>(R, yb[par], pv[par], k, kb, wave, i);
+        __syncthreads();
       }
     }
     if (kind < 2) {
