@@ -239,8 +239,9 @@ def summarize(stats_csv, fetch_csv, write_csv, command, pmc_command):
             out.append(f"| `{short}` | {fe[nm][1]} | {rf / 1e9:.4f} | {rw / 1e9:.4f} | "
                        f"{(rf + rw) * fe[nm][1] / 1e9:.2f} |")
         # the four solves of the sample (one warm-up + three timed) and its six SpMV
-        solve_k = ("k_gather", "k_solve_fwd", "k_lfwd_init", "k_lfwd_step", "k_solve_bwd",
-                   "k_lbwd_step", "k_lbwd_finish", "k_scatter")
+        solve_k = ("k_gather", "k_solve_fwd", "k_lfwd_init", "k_lfwd_step", "k_lfwd_l21",
+                   "k_lfwd_l21_reduce", "k_solve_bwd", "k_lbwd_l21", "k_lbwd_l21_reduce",
+                   "k_lbwd_push", "k_scatter")
         tot = lambda nm: fe[nm][0] * f_fac + wr.get(nm, [0.0, 1])[0] * w_fac
         sv = [nm for nm in keys if base_name(nm) in solve_k]
         if sv:
@@ -250,12 +251,17 @@ def summarize(stats_csv, fetch_csv, write_csv, command, pmc_command):
         if sp:
             out += [f"- spmv_hbm_bytes_per_dispatch: {sum(tot(nm) for nm in sp) / sum(fe[nm][1] for nm in sp):.6e}"
                     f" (average of B x and the fused A x, B x)"]
-        sch = [nm for nm in keys if "k_gemm_lt<256, double>" in nm]
+        # the update products: k_gemm_lt (left-looking, small contribution blocks)
+        # and k_gemm_cb128 (contribution blocks on 128 x 128 tiles), FP64
+        sch = [nm for nm in keys if "k_gemm_lt<256, double>" in nm or "k_gemm_cb128<256, double>" in nm]
         if sch:
-            nm = sch[0]
-            per = fe[nm][0] * f_fac / fe[nm][1] + wr[nm][0] * w_fac / wr[nm][1]
+            launches = sum(fe[nm][1] for nm in sch)
+            per = sum(tot(nm) for nm in sch) / launches
             out += ["", f"- k_gemm_lt_hbm_bytes_per_launch: {per:.6e}",
-                    f"- k_gemm_lt_launches: {fe[nm][1]}",
+                    f"- k_gemm_lt_launches: {launches}",
+                    "- (k_gemm_lt and k_gemm_cb128 together: "
+                    + ", ".join(f"{base_name(nm)} {fe[nm][1]} launches, {tot(nm) / fe[nm][1]:.4e} B each"
+                                for nm in sch) + ")",
                     f"- kernel_source_sha256: `{kernel_source_hash()}`"]
         out.append("")
     print("\n".join(out))
@@ -396,7 +402,8 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_gemm_lt (left-looking and contribution-block products, FP64 v_mfma_f64_16x16x4)",
+            "kernel": "update products: k_gemm_lt (left-looking, contribution blocks below 384 rows) "
+                      "and k_gemm_cb128 (contribution blocks on 128x128 tiles), FP64 v_mfma_f64_16x16x4",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
