@@ -287,19 +287,21 @@ static void build_schedule(Pencil& P) {
       for (int64_t r = 0; r < S.nf(s); r += kSolveChunk) { sched.push_back(s); sched.push_back((int32_t)r); }
     }
     sl.init_cnt = (int32_t)((sched.size() - sl.init_off) / 2);
-    for (const StepPlan& sp : lp.steps) {
+    // the chain steps take the tiles two at a time (tiles t and t + 1, t even)
+    for (size_t qs = 0; qs < lp.steps.size(); qs += 2) {
+      const StepPlan& sp = lp.steps[qs];
       SolveStep ss;
       ss.t = sp.t;
       ss.nfronts = sp.nfronts;
       const int64_t k0 = sp.t * (int64_t)kNB;
-      // forward: rows below the tile inside the pivot block only (the rows below
-      // the block take the level's L21 launches)
+      // forward: rows below the two tiles inside the pivot block only (the rows
+      // below the block take the level's L21 launches)
       align2();
       ss.fwd_off = (int32_t)sched.size();
       for (int32_t q = 0; q < sp.nfronts; q++) {
         const int32_t s = sched[lp.large_off + q];
         const int64_t ns = S.ns(s);
-        const int64_t rb = std::min<int64_t>(k0 + kNB, ns);
+        const int64_t rb = std::min<int64_t>(k0 + 2 * kNB, ns);
         if (rb >= ns) { sched.push_back(s); sched.push_back((int32_t)ns); }
         for (int64_t r = rb; r < ns; r += kNB) { sched.push_back(s); sched.push_back((int32_t)r); }
       }

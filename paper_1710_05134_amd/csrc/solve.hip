@@ -225,69 +225,123 @@ __device__ inline void wave_column_sums(double (&v)[kNB], int lane) {
 constexpr int kChainBlk = 64;                      // rows / columns of a chain-step task
 constexpr int kChainThreads = 64 + 4 * kChainBlk;  // wave 0: the tile; then four threads per row
 
-// Forward tile step t of the large fronts of a level, one launch.  Every
-// workgroup solves L_tt z = P_t r_t itself (wave 0, the 64x64 tile in registers,
-// row = lane) while its other threads load their share of the kChainBlk rows of
-// the pivot block below the tile (four threads per row, 16 columns each); then
-// R_i -= L(i, tile) z.  The workgroup of a front's first row chunk also writes
-// y = D^{-1} z, and z itself for the rows below the pivot block.  A front without
-// pivot-block rows below the tile has one task with an empty row range.
+// Forward tile steps t and t + 1 of the large fronts of a level, one launch.
+// Every workgroup solves L_tt z = P_t r_t itself (wave 0, the tile in registers,
+// row = lane), brings tile t+1's right-hand side up to date with it (four threads
+// per row of tile t+1), solves L_{t+1,t+1} z' = P_{t+1} r'_{t+1} (wave 0, tile t+1
+// staged in LDS by the other threads while tile t was solved), then updates its
+// kChainBlk rows of the pivot block below both tiles with z and z' (four threads
+// per row, 16 columns of each tile).  The workgroup of a front's first row chunk
+// writes y = D^{-1} z and z itself (for the rows below the pivot block) of both
+// tiles.  Without a tile t + 1 (the front's last tile) only tile t is done.  A
+// front without pivot-block rows below the two tiles has one task with an empty
+// row range.
 template <typename T>
 __global__ __launch_bounds__(kChainThreads) void k_lfwd_step(FrontMeta M, const Int2* tasks, int t,
                                                              const T* L, const double* __restrict__ D,
                                                              const double* __restrict__ E,
                                                              const int32_t* __restrict__ tperm,
                                                              double* R, double* ye, double* xe) {
-  __shared__ double z[kNB];
+  __shared__ double z0[kNB], z1[kNB], r1[kNB];
+  __shared__ double tl1[kNB][kNB + 1];   // tile t + 1, [row][column]
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, r0 = tk.b;
   const int tid = threadIdx.x, lane = tid & 63;
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
-  const int k0 = t * kNB, kb = min(kNB, ns - k0);
+  const int k0 = t * kNB, kb0 = min(kNB, ns - k0);
+  const int k1 = k0 + kb0, kb1 = min(kNB, ns - k1);
+  const bool two = kb1 > 0;
   const T* Lp = L + M.lptr[s];
   double* Rs = R + M.rptr[s];
-  const int u = tid - 64, qr = u & 3;
-  const int i = r0 + (u >> 2);
-  double v[16];
-  double ri = 0.0;
+  const int u = tid - 64, qr = u & 3, rr = u >> 2;
+  const int i = r0 + rr;
+  double va[16], vb[16], vc[16];
+  double ra = 0.0, ri = 0.0;
   // unconditional loads from clamped (valid) addresses, masked afterwards, so that
   // they are all in flight together
   if (tid < 64) {
-    const int lc = min(lane, kb - 1);
+    const int lc = min(lane, kb0 - 1);
     double Lv[kNB];
 #pragma unroll
-    for (int p = 0; p < kNB; p++) Lv[p] = (double)Lp[(k0 + lc) + (int64_t)(k0 + min(p, kb - 1)) * nf];
+    for (int p = 0; p < kNB; p++) Lv[p] = (double)Lp[(k0 + lc) + (int64_t)(k0 + min(p, kb0 - 1)) * nf];
     // strictly lower part of the tile only, so that every step updates all lanes
 #pragma unroll
-    for (int p = 0; p < kNB; p++) Lv[p] = (lane < kb && p < lane) ? Lv[p] : 0.0;
-    double zl = lane < kb ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
+    for (int p = 0; p < kNB; p++) Lv[p] = (lane < kb0 && p < lane) ? Lv[p] : 0.0;
+    double zl = lane < kb0 ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
 #pragma unroll
     for (int p = 0; p < kNB; p++) zl = fma(-Lv[p], lane_value(zl, p), zl);
-    z[lane] = zl;   // zero beyond kb
+    z0[lane] = zl;   // zero beyond kb0
   } else {
     const int ic = min(i, ns - 1);
 #pragma unroll
-    for (int c = 0; c < 16; c++) v[c] = (double)Lp[ic + (int64_t)(k0 + min(qr * 16 + c, kb - 1)) * nf];
-    // this row's right-hand side, read before the barrier: rows below the tile are
+    for (int c = 0; c < 16; c++) vb[c] = (double)Lp[ic + (int64_t)(k0 + min(qr * 16 + c, kb0 - 1)) * nf];
+    if (two) {
+      const int ia = k1 + min(rr, kb1 - 1);
+#pragma unroll
+      for (int c = 0; c < 16; c++) va[c] = (double)Lp[ia + (int64_t)(k0 + min(qr * 16 + c, kb0 - 1)) * nf];
+#pragma unroll
+      for (int c = 0; c < 16; c++) vc[c] = (double)Lp[ic + (int64_t)(k1 + min(qr * 16 + c, kb1 - 1)) * nf];
+      // tile t + 1 into LDS: row u mod 64, 16 columns from 16 (u / 64)
+      const int tr = u & 63, tc0 = (u >> 6) * 16;
+      double w[16];
+#pragma unroll
+      for (int c = 0; c < 16; c++)
+        w[c] = (double)Lp[(k1 + min(tr, kb1 - 1)) + (int64_t)(k1 + min(tc0 + c, kb1 - 1)) * nf];
+#pragma unroll
+      for (int c = 0; c < 16; c++) tl1[tr][tc0 + c] = w[c];
+      if (qr == 0 && rr < kb1) ra = Rs[k1 + rr];
+    }
+    // the row's right-hand side, read before the barrier: rows below the tiles are
     // written by their own workgroup only
     if (qr == 0 && i < ns) ri = Rs[i];
   }
   __syncthreads();
+  if (two) {
+    if (tid >= 64) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; c++) acc = fma(va[c], z0[qr * 16 + c], acc);
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      if (qr == 0) r1[rr] = ra - acc;   // stored (unswapped) row order of tile t + 1
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double Lw[kNB];
+#pragma unroll
+      for (int p = 0; p < kNB; p++) Lw[p] = (lane < kb1 && p < lane) ? tl1[lane][p] : 0.0;
+      double zl = lane < kb1 ? r1[tperm[f0 + k1 + lane]] : 0.0;
+#pragma unroll
+      for (int p = 0; p < kNB; p++) zl = fma(-Lw[p], lane_value(zl, p), zl);
+      z1[lane] = zl;
+    }
+    __syncthreads();
+  }
   if (tid >= 64) {
     double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < 16; c++) acc = fma(v[c], z[qr * 16 + c], acc);
+    for (int c = 0; c < 16; c++) acc = fma(vb[c], z0[qr * 16 + c], acc);
+    if (two) {
+#pragma unroll
+      for (int c = 0; c < 16; c++) acc = fma(vc[c], z1[qr * 16 + c], acc);
+    }
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);
     if (qr == 0 && i < ns) Rs[i] = ri - acc;
   }
-  // the first chunk's workgroup: y = D^{-1} z, and z itself for the rows below the
-  // pivot block (xe of the pivots is free once the level's gather has read it)
-  if (r0 == k0 + kb && tid < kb) {
-    ye[f0 + k0 + tid] = apply_dinv(D, E, z, f0 + k0 + tid, tid, kb);
-    xe[f0 + k0 + tid] = z[tid];
+  // the first chunk's workgroup: y = D^{-1} z and z itself (xe of the pivots is free
+  // once the level's gather has read it)
+  if (r0 == (two ? k1 + kb1 : k1)) {
+    if (tid < kb0) {
+      ye[f0 + k0 + tid] = apply_dinv(D, E, z0, f0 + k0 + tid, tid, kb0);
+      xe[f0 + k0 + tid] = z0[tid];
+    }
+    if (two && tid < kb1) {
+      ye[f0 + k1 + tid] = apply_dinv(D, E, z1, f0 + k1 + tid, tid, kb1);
+      xe[f0 + k1 + tid] = z1[tid];
+    }
   }
 }
 
@@ -343,63 +397,119 @@ __global__ __launch_bounds__(kL21Rows) void k_lfwd_l21_reduce(FrontMeta M, const
   R[M.rptr[s] + i] -= sum;
 }
 
-// Backward tile step t (tiles in reverse), one launch, in the form that pushes each
-// finished tile into the columns before it.  Every workgroup solves L_tt^T w = y_t
-// itself (wave 0: the tile through LDS, column = lane), y_t having received the
-// contributions of all later tiles and of the rows below the pivot block; then its
-// other threads subtract, for kChainBlk columns j < k0 of the pivot block (four
-// threads per column, 16 tile rows each), y_j -= sum_i L(k0 + i, j) x_i, the rows
-// i of the tile in their stored (unswapped) order.  The workgroup of the first
-// column chunk writes x(f0 + k0 + perm[q]) = w_q.  Tile 0 has one task with an
-// empty column range.
+// Backward tile steps t + 1 and t (pairs in reverse), one launch, in the form that
+// pushes each finished tile into the columns before it.  Every workgroup solves
+// L_{t+1,t+1}^T w' = y_{t+1} itself (wave 0: the tile through LDS, column = lane),
+// y_{t+1} having received the contributions of all later tiles and of the rows
+// below the pivot block; its other threads push w' into tile t's y (four threads
+// per column), wave 0 solves L_tt^T w = y_t (tile t staged in LDS meanwhile), and
+// the other threads subtract, for kChainBlk columns j < k0 of the pivot block,
+// y_j -= sum_i L(k0 + i, j) x_i + sum_i L(k1 + i, j) x'_i, the rows of each tile
+// in their stored (unswapped) order.  The workgroup of the first column chunk
+// writes x(f0 + k + perm[q]) = w_q of both tiles.  Without a tile t + 1 only tile t
+// is done; tile 0 has one task with an empty column range.
 template <typename T>
 __global__ __launch_bounds__(kChainThreads) void k_lbwd_push(FrontMeta M, const Int2* tasks, int t,
                                                              const T* L,
                                                              const int32_t* __restrict__ tperm,
                                                              double* ye, double* xe) {
-  __shared__ double tl[kNB][kNB + 1];
-  __shared__ double xs[kNB];
+  __shared__ double tl[kNB][kNB + 1];    // tile t + 1 (wave 0's transposition buffer)
+  __shared__ double tl0[kNB][kNB + 1];   // tile t, [row][column]
+  __shared__ double xs0[kNB], xs1[kNB], yt[kNB];
   const Int2 tk = tasks[blockIdx.x];
   const int s = tk.a, c0 = tk.b;
   const int tid = threadIdx.x, lane = tid & 63;
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
-  const int k0 = t * kNB, kb = min(kNB, ns - k0);
+  const int k0 = t * kNB, kb0 = min(kNB, ns - k0);
+  const int k1 = k0 + kb0, kb1 = min(kNB, ns - k1);
+  const bool two = kb1 > 0;
   const T* Lp = L + M.lptr[s];
-  const int u = tid - 64, qr = u & 3;
-  const int j = c0 + (u >> 2);
-  double v[16];
+  const int u = tid - 64, qr = u & 3, jj = u >> 2;
+  const int j = c0 + jj;
+  double va[16], vb[16], vc[16];
+  double yv = 0.0;
   if (tid < 64) {
-    // row lane of the tile into LDS (coalesced loads), then column lane from it;
-    // one wave: its LDS writes and reads complete in order
-    const int lc = min(lane, kb - 1);
-    double Lr[kNB];
+    if (two) {
+      // row lane of tile t + 1 into LDS (coalesced loads), then column lane from it;
+      // one wave: its LDS writes and reads complete in order
+      const int lc = min(lane, kb1 - 1);
+      double Lr[kNB];
 #pragma unroll
-    for (int p = 0; p < kNB; p++) Lr[p] = (double)Lp[(k0 + lc) + (int64_t)(k0 + min(p, kb - 1)) * nf];
-    double g = lane < kb ? ye[f0 + k0 + lane] : 0.0;
-    const int tp = lane < kb ? tperm[f0 + k0 + lane] : 0;
+      for (int p = 0; p < kNB; p++) Lr[p] = (double)Lp[(k1 + lc) + (int64_t)(k1 + min(p, kb1 - 1)) * nf];
+      double g = lane < kb1 ? ye[f0 + k1 + lane] : 0.0;
+      const int tp = lane < kb1 ? tperm[f0 + k1 + lane] : 0;
 #pragma unroll
-    for (int p = 0; p < kNB; p++) tl[lane][p] = Lr[p];
-    double Lc[kNB];
+      for (int p = 0; p < kNB; p++) tl[lane][p] = Lr[p];
+      double Lc[kNB];
 #pragma unroll
-    for (int p = 0; p < kNB; p++) Lc[p] = (p > lane && p < kb) ? tl[p][lane] : 0.0;
-    // w_q = g_q - sum_{p > q} L(p, q) w_p, p descending (zero beyond kb)
+      for (int p = 0; p < kNB; p++) Lc[p] = (p > lane && p < kb1) ? tl[p][lane] : 0.0;
+      // w_q = g_q - sum_{p > q} L(p, q) w_p, p descending (zero beyond kb1)
 #pragma unroll
-    for (int p = kNB - 1; p >= 0; p--) g = fma(-Lc[p], lane_value(g, p), g);
-    xs[lane] = 0.0;
-    if (lane < kb) xs[tp] = g;
-    if (c0 == 0 && lane < kb) xe[f0 + k0 + tp] = g;
+      for (int p = kNB - 1; p >= 0; p--) g = fma(-Lc[p], lane_value(g, p), g);
+      xs1[lane] = 0.0;
+      if (lane < kb1) xs1[tp] = g;
+      if (c0 == 0 && lane < kb1) xe[f0 + k1 + tp] = g;
+    }
   } else {
+    // tile t + 1's push into tile t's columns: column jj of tile t, 16 rows of t + 1
+    if (two) {
+#pragma unroll
+      for (int c = 0; c < 16; c++)
+        va[c] = (double)Lp[(k1 + min(qr * 16 + c, kb1 - 1)) + (int64_t)(k0 + min(jj, kb0 - 1)) * nf];
+    }
+    if (qr == 0 && jj < kb0) yv = ye[f0 + k0 + jj];
+    // this chunk's columns j < k0: 16 rows of each tile
     const int jc = min(j, max(k0 - 1, 0));
 #pragma unroll
-    for (int c = 0; c < 16; c++) v[c] = (double)Lp[(k0 + min(qr * 16 + c, kb - 1)) + (int64_t)jc * nf];
+    for (int c = 0; c < 16; c++) vb[c] = (double)Lp[(k0 + min(qr * 16 + c, kb0 - 1)) + (int64_t)jc * nf];
+    if (two) {
+#pragma unroll
+      for (int c = 0; c < 16; c++) vc[c] = (double)Lp[(k1 + min(qr * 16 + c, kb1 - 1)) + (int64_t)jc * nf];
+    }
+    // tile t into LDS: row u mod 64, 16 columns from 16 (u / 64)
+    const int tr = u & 63, tc0 = (u >> 6) * 16;
+    double w[16];
+#pragma unroll
+    for (int c = 0; c < 16; c++)
+      w[c] = (double)Lp[(k0 + min(tr, kb0 - 1)) + (int64_t)(k0 + min(tc0 + c, kb0 - 1)) * nf];
+#pragma unroll
+    for (int c = 0; c < 16; c++) tl0[tr][tc0 + c] = w[c];
+  }
+  __syncthreads();
+  if (tid >= 64) {
+    double acc = 0.0;
+    if (two) {
+#pragma unroll
+      for (int c = 0; c < 16; c++) acc = fma(va[c], xs1[qr * 16 + c], acc);
+    }
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (qr == 0) yt[jj] = yv - acc;   // pivot order of tile t; zero-based garbage beyond kb0
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double Lc[kNB];
+#pragma unroll
+    for (int p = 0; p < kNB; p++) Lc[p] = (p > lane && p < kb0) ? tl0[p][lane] : 0.0;
+    double g = lane < kb0 ? yt[lane] : 0.0;
+    const int tp = lane < kb0 ? tperm[f0 + k0 + lane] : 0;
+#pragma unroll
+    for (int p = kNB - 1; p >= 0; p--) g = fma(-Lc[p], lane_value(g, p), g);
+    xs0[lane] = 0.0;
+    if (lane < kb0) xs0[tp] = g;
+    if (c0 == 0 && lane < kb0) xe[f0 + k0 + tp] = g;
   }
   __syncthreads();
   if (tid >= 64) {
     double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < 16; c++) acc = fma(v[c], xs[qr * 16 + c], acc);
+    for (int c = 0; c < 16; c++) acc = fma(vb[c], xs0[qr * 16 + c], acc);
+    if (two) {
+#pragma unroll
+      for (int c = 0; c < 16; c++) acc = fma(vc[c], xs1[qr * 16 + c], acc);
+    }
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);
     if (qr == 0 && j < k0) ye[f0 + j] -= acc;

@@ -9,13 +9,13 @@
 
 namespace kth {
 
-struct SolveStep {
+struct SolveStep {               // tiles t and t + 1 (t even) of the level's large fronts
   int32_t t;
   int32_t nfronts;               // active large fronts (prefix of the level's list)
   int32_t fwd_off, fwd_cnt;      // Int2 (front, first row) tasks of 64 pivot-block rows below
-                                 // the tile, in row order per front; (front, ns) if none
-  int32_t bwd_off, bwd_cnt;      // Int2 (front, first column) tasks of 64 columns before the
-                                 // tile, first chunk first; (front, 0) for tile 0
+                                 // the two tiles, in row order per front; (front, ns) if none
+  int32_t bwd_off, bwd_cnt;      // Int2 (front, first column) tasks of 64 columns before
+                                 // tile t, first chunk first; (front, 0) for tile 0
 };
 
 struct SolveLevel {
