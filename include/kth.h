@@ -59,7 +59,12 @@ typedef void (*kth_free_fn)(void* ptr, void* user);
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run on,
  * or NULL for a stream owned by the context.  alloc/free: device allocator (both
- * NULL: hipMalloc / hipFree); `user` is passed back to them.
+ * NULL: hipMalloc / hipFree behind a stream-ordered block cache); `user` is passed
+ * back to them.  alloc returns NULL on failure (the call then fails with
+ * KTH_ENOMEM); free is called once the stream that used the block (the context's,
+ * or a kth_eig_batch worker's) has finished with it, so the allocator may reuse it
+ * at once.  Python: Context(torch_allocator=True) routes both to torch's caching
+ * allocator on the context's stream.
  * Fails with KTH_EDEVICE if the device is not a gfx950 GPU. */
 kth_status kth_ctx_create(int device, void* hip_stream, kth_alloc_fn alloc, kth_free_fn free_fn,
                           void* user, kth_ctx* out);

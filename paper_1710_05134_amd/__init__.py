@@ -144,12 +144,44 @@ def kth_analyze(rowptr, col, check_symmetry=False, want_perm=False):
     return (d, perm) if want_perm else d
 
 
-class Context:
-    """kth_ctx: device, stream (torch's current stream if torch is given one)."""
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
-    def __init__(self, device: int = 0, hip_stream: int | None = None):
+
+class Context:
+    """kth_ctx: device and stream (a raw hipStream_t, e.g. torch's
+    ``torch.cuda.current_stream().cuda_stream``).  With ``torch_allocator=True`` the
+    library's device memory comes from torch's caching allocator
+    (``caching_allocator_alloc`` / ``caching_allocator_delete`` on that stream),
+    through the allocator hooks of kth_ctx_create, and the context runs on torch's
+    current stream unless ``hip_stream`` names another; torch must be imported first."""
+
+    def __init__(self, device: int = 0, hip_stream: int | None = None, torch_allocator: bool = False):
+        self._hooks = None
+        alloc = free = None
+        if torch_allocator:
+            import torch
+            dev = int(device)
+            if hip_stream is None:   # run on torch's current stream: its pool's order
+                hip_stream = torch.cuda.current_stream(dev).cuda_stream
+
+            def _alloc(nbytes, _user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(max(int(nbytes), 1), dev, hip_stream)
+                except Exception:
+                    return None   # the library reports KTH_ENOMEM
+
+            def _free(ptr, _user):
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except Exception:
+                    pass
+
+            self._hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))   # kept alive with the context
+            alloc, free = self._hooks
         h = C.c_void_p()
-        _check(lib().kth_ctx_create(device, hip_stream, None, None, None, C.byref(h)))
+        _check(lib().kth_ctx_create(device, hip_stream, C.cast(alloc, C.c_void_p) if alloc else None,
+                                    C.cast(free, C.c_void_p) if free else None, None, C.byref(h)))
         self.h = h
 
     def close(self):
@@ -382,22 +414,33 @@ def kth_debug_mfma_probe(A, B):
 def eig_function():
     """torch.autograd.Function over (a_val, b_val) -> lambda_k: forward through kth_eig on
     the pencil's pattern(s), backward through kth_eig_backward (Hellmann-Feynman).
-    Tensors are float64 on the host (PyTorch only carries them).  Usage:
+    float64 tensors on the host, or on the pencil's GPU: device values go to the
+    library as device pointers (kth_pencil_set_values with KTH_DEVICE_PTRS, after
+    torch's current stream is synchronised); lambda_k and the gradients come back on
+    the values' device.  Usage:
         F = eig_function(); lam = F.apply(a, b, pencil, k, opts_or_None)"""
     import torch
 
     class KthEig(torch.autograd.Function):
         @staticmethod
         def forward(ctx, a_val, b_val, pencil, k, opts):
-            pencil.set_values(a_val.detach().to("cpu", torch.float64).numpy(),
-                              b_val.detach().to("cpu", torch.float64).numpy())
+            dev = a_val.device
+            if a_val.is_cuda:
+                a = a_val.detach().to(torch.float64).contiguous()
+                b = b_val.detach().to(device=dev, dtype=torch.float64).contiguous()
+                torch.cuda.current_stream(dev).synchronize()
+                pencil.set_values_device(a.data_ptr(), b.data_ptr())
+            else:
+                pencil.set_values(a_val.detach().to("cpu", torch.float64).numpy(),
+                                  b_val.detach().to("cpu", torch.float64).numpy())
             lam, x, _ = pencil.eig(int(k), opts=opts)
-            ctx.pencil, ctx.lam, ctx.x = pencil, lam, x
-            return torch.tensor(lam, dtype=torch.float64)
+            ctx.pencil, ctx.lam, ctx.x, ctx.dev = pencil, lam, x, dev
+            return torch.tensor(lam, dtype=torch.float64, device=dev)
 
         @staticmethod
         def backward(ctx, g):
             ga, gb = ctx.pencil.backward(ctx.lam, ctx.x, float(g))
-            return torch.from_numpy(ga), torch.from_numpy(gb), None, None, None
+            return (torch.from_numpy(ga).to(ctx.dev), torch.from_numpy(gb).to(ctx.dev), None, None,
+                    None)
 
     return KthEig

@@ -50,7 +50,13 @@ void* Ctx::alloc(size_t bytes) {
 void Ctx::release(void* p, size_t bytes) {
   if (!p) return;
   cur_bytes -= (double)bytes;
-  if (ffn) { ffn(p, user); return; }
+  if (ffn) {
+    // the caller's allocator may hand the block out again at once: the work that
+    // used it (on this context's stream, or a batch worker's) must be finished
+    (void)hipStreamSynchronize(stream);
+    ffn(p, user);
+    return;
+  }
   auto it = sizes.find(p);
   const size_t got = it != sizes.end() ? it->second : bytes;
   if (it != sizes.end()) sizes.erase(it);

@@ -50,6 +50,27 @@ def main():
         an = (a.grad[q].item() + a.grad[q2].item()) / 3.0
         assert abs(fd - an) <= 1e-7 + 1e-4 * abs(an), (i, j, fd, an)
         print(f"  pair ({i},{j}): fd {fd:.9f} autograd {an:.9f}", flush=True)
+    # device tensors: the same lambda_k bit for bit, the same gradients, on the GPU
+    a_d = torch.tensor(p.a_val, dtype=torch.float64, device="cuda", requires_grad=True)
+    b_d = torch.tensor(p.b_val, dtype=torch.float64, device="cuda", requires_grad=True)
+    lam_d = F.apply(a_d, b_d, P, k, opts)
+    (3.0 * lam_d).backward()
+    assert lam_d.is_cuda and lam_d.item() == lam.item()
+    assert a_d.grad.is_cuda
+    assert np.array_equal(a_d.grad.cpu().numpy(), a.grad.numpy())
+    assert np.array_equal(b_d.grad.cpu().numpy(), b.grad.numpy())
+    print("  device tensors: same lambda_k and gradients", flush=True)
+    # the library's device memory from torch's caching allocator
+    before = torch.cuda.memory_allocated(0)
+    ctx_t = K.Context(0, torch_allocator=True)
+    P_t = K.Pencil.from_pencilgen(ctx_t, p)
+    lam_t, _, info_t = P_t.eig(k, opts=opts)
+    held = torch.cuda.memory_allocated(0) - before
+    assert info_t["k_validated"] == k and lam_t == lam.item(), (lam_t, lam.item())
+    assert held > 0, held
+    P_t.close()
+    ctx_t.close()
+    print(f"  torch caching allocator: same lambda_k, {held} bytes held through torch", flush=True)
     print("autograd check ok", flush=True)
 
 
