@@ -38,8 +38,10 @@ struct FactStats {
 constexpr int kSmallMaxNf = 128;
 // Pivot-tile width (and panel width) of large fronts.
 constexpr int kNB = 64;
-// Column chunk of the large-front assembly kernel.
+// Column chunk and row block of one large-front assembly task (the row block is
+// the 64 x 8 rows one wavefront gathers per column in one pass).
 constexpr int kAsmCols = 16;
+constexpr int kAsmRows = 512;
 // Rows per workgroup of the panel triangular solve.
 constexpr int kTrsmRows = 64;
 // Rows per gather task of the large-front solve.

@@ -188,8 +188,18 @@ static void build_schedule(Pencil& P) {
     P.tsize = std::max(P.tsize, toff);
     align2();
     lp.init_off = (int32_t)sched.size();
-    for (int32_t s : large)
-      for (int64_t c0 = 0; c0 < S.nf(s); c0 += kAsmCols) { sched.push_back(s); sched.push_back((int32_t)c0); }
+    // assembly tasks: (front, chunk * nrb + row block) for the column chunks of
+    // kAsmCols and the row blocks of kAsmRows that meet the lower triangle
+    for (int32_t s : large) {
+      const int64_t nf = S.nf(s), nrb = (nf + kAsmRows - 1) / kAsmRows;
+      const int64_t nch = (nf + kAsmCols - 1) / kAsmCols;
+      if (nch * nrb > INT32_MAX) throw Error(KTH_EINVAL, "front too large for the assembly schedule");
+      for (int64_t ch = 0; ch < nch; ch++)
+        for (int64_t rb = ch * kAsmCols / kAsmRows; rb < nrb; rb++) {
+          sched.push_back(s);
+          sched.push_back((int32_t)(ch * nrb + rb));
+        }
+    }
     lp.init_cnt = (int32_t)((sched.size() - lp.init_off) / 2);
     int64_t tmax = 0;
     for (int32_t s : large) tmax = std::max<int64_t>(tmax, (S.ns(s) + kNB - 1) / kNB);

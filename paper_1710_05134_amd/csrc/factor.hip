@@ -627,54 +627,62 @@ __global__ __launch_bounds__(NT) void k_front_init(FrontMeta M, const Int2* task
   L += bidx * bt.sL; U += bidx * bt.sU;
   const double* sigma_dev = bt.sig + bidx;
   const Int2 tk = tasks[blockIdx.x];
-  const int s = tk.a, c0 = tk.b;
+  const int s = tk.a;
   const FrontRef<T> f = front_ref<T>(M, s, L, U);
-  const int c1 = min(c0 + kAsmCols, f.nf);
+  // the task is column chunk c0 .. c1 - 1, rows r0 .. r1 - 1 (lower triangle only)
+  const int nrb = (f.nf + kAsmRows - 1) / kAsmRows;
+  const int chunk = tk.b / nrb, rb = tk.b - chunk * nrb;
+  const int c0 = chunk * kAsmCols, c1 = min(c0 + kAsmCols, f.nf);
+  const int r0 = rb * kAsmRows, r1 = min(r0 + kAsmRows, f.nf);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
   const double sigma = *sigma_dev;
-  // every entry (i >= j) of the chunk is written once: the sum of the children's
+  // every entry (i >= j) of the piece is written once: the sum of the children's
   // update-block entries that map to it (through their inverse maps), children in
   // list order; a root's update block does not exist (nu == 0, no columns >= ns)
   const int64_t q0 = M.cptr[s], q1 = M.cptr[s + 1];
-  constexpr int RU = 8;   // row groups of 64 per lane and iteration: independent load chains
+  constexpr int RU = kAsmRows / 64;   // row groups of 64 per lane: independent load chains
   for (int j = c0 + wave; j < c1; j += NW) {
-    for (int i0 = j; i0 < f.nf; i0 += 64 * RU) {
-      T v[RU];
+    const int i0 = max(j, r0);
+    if (i0 >= r1) continue;
+    T v[RU];
 #pragma unroll
-      for (int u = 0; u < RU; u++) v[u] = 0.0;
-      for (int64_t q = q0; q < q1; q++) {
-        const int c = M.clist[q];
-        const int32_t* inv = M.imap + M.iptr[c];
-        const int bj = inv[j];
-        if (bj < 0) continue;
-        const int nuc = (int)(M.rptr[c + 1] - M.rptr[c] - (M.sfirst[c + 1] - M.sfirst[c]));
-        const T* Uc = U + M.uptr[c] + (int64_t)bj * nuc;
-        int ai[RU];
+    for (int u = 0; u < RU; u++) v[u] = 0.0;
+    for (int64_t q = q0; q < q1; q++) {
+      const int c = M.clist[q];
+      const int32_t* inv = M.imap + M.iptr[c];
+      const int bj = inv[j];
+      if (bj < 0) continue;
+      const int nuc = (int)(M.rptr[c + 1] - M.rptr[c] - (M.sfirst[c + 1] - M.sfirst[c]));
+      const T* Uc = U + M.uptr[c] + (int64_t)bj * nuc;
+      int ai[RU];
 #pragma unroll
-        for (int u = 0; u < RU; u++) ai[u] = inv[min(i0 + 64 * u + lane, f.nf - 1)];
-        T uv[RU];
+      for (int u = 0; u < RU; u++) ai[u] = inv[min(i0 + 64 * u + lane, r1 - 1)];
+      T uv[RU];
 #pragma unroll
-        for (int u = 0; u < RU; u++) uv[u] = Uc[max(ai[u], 0)];   // clamped: a valid entry
+      for (int u = 0; u < RU; u++) uv[u] = Uc[max(ai[u], 0)];   // clamped: a valid entry
 #pragma unroll
-        for (int u = 0; u < RU; u++)
-          if (ai[u] >= 0) v[u] += uv[u];
-      }
+      for (int u = 0; u < RU; u++)
+        if (ai[u] >= 0) v[u] += uv[u];
+    }
 #pragma unroll
-      for (int u = 0; u < RU; u++) {
-        const int i = i0 + 64 * u + lane;
-        if (i < f.nf) *f.at(i, j) = v[u];
-      }
+    for (int u = 0; u < RU; u++) {
+      const int i = i0 + 64 * u + lane;
+      if (i < r1) *f.at(i, j) = v[u];
     }
   }
   __syncthreads();
-  // original entries of A - sigma B (fully-summed columns only)
-  if (c0 < f.ns) {
-    const int64_t f0 = M.sfirst[s];
-    const int64_t e1 = M.acptr[f0 + min(c1, f.ns)];
-    for (int64_t e = M.acptr[f0 + c0] + tid; e < e1; e += NT) {
+  // original entries of A - sigma B in the piece (fully-summed columns only): the
+  // entries of column j sit at acptr[f0 + j] .. in the front at row + j * nf
+  const int64_t f0 = M.sfirst[s];
+  for (int j = c0 + wave; j < min(c1, f.ns); j += NW) {
+    const int64_t e1 = M.acptr[f0 + j + 1], base = (int64_t)j * f.nf;
+    for (int64_t e = M.acptr[f0 + j] + lane; e < e1; e += 64) {
+      const int64_t dst = M.adst[e];
+      const int64_t i = dst - base;
+      if (i < r0 || i >= r1) continue;
       const int64_t p = M.asrc[e];
-      f.Lp[M.adst[e]] += fma(-sigma, bval[p], aval[p]);
+      f.Lp[dst] += fma(-sigma, bval[p], aval[p]);
     }
   }
 }
