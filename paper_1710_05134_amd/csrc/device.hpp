@@ -52,6 +52,10 @@ constexpr int kL21Rows = 256;
 constexpr int kL21Cols = 256;
 // Schur-update output tile.
 constexpr int kTile = 64;
+// Task flag of a left-looking rows-below launch (mode 1) for pivot tile t: the
+// task (front, row | kLaFlag) is the diagonal block of tile t + 1 at the same depth
+// t * kNB (its update without tile t's columns, applied ahead).
+constexpr int kLaFlag = 1 << 30;
 // fronts whose contribution block has at least this many rows update it on
 // 128 x 128 tiles (k_gemm_cb128)
 constexpr int kCb128MinNu = 384;
@@ -59,10 +63,6 @@ constexpr int kCb128MinNu = 384;
 constexpr int kSegK = 256;
 // workgroups a split-depth left-looking launch aims at (four per CU)
 constexpr int kLLTargetWgs = 1024;
-// the diagonal block's update (one output tile per front, on the critical path)
-// takes segments of at least kSegKDiag columns, at most kMaxSegDiag of them
-constexpr int kSegKDiag = 32;
-constexpr int kMaxSegDiag = 64;
 
 struct Int2 { int32_t a, b; };
 
@@ -96,17 +96,21 @@ template <typename T>
 void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count, int32_t t,
                         const Batch& bt, int nb, T* L, double* D, double* E, int32_t* tperm,
                         T* tinv, FactStats* st, hipStream_t s);
+// Panel solve of the rows below pivot tile t, tasks (front, first row).  With upd,
+// a task whose rows are the next tile's (first row < ns) also applies this tile's
+// columns to the next tile's diagonal block: C -= L W^T over the tile's depth.
 template <typename T>
 void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t,
                        const Batch& bt, int nb, T* L, T* W, const double* D, const double* E,
-                       const int32_t* tperm, const T* tinv, FactStats* st, hipStream_t s);
+                       const int32_t* tperm, const T* tinv, FactStats* st, int upd, hipStream_t s);
 // Left-looking updates C -= L W^T (W = L D panel-shaped): mode 0/1, column block of
 // pivot tile t for tasks (front, first row) -- mode 0 the tile's diagonal block,
 // mode 1 rows below it; mode 2, tasks (front, lower tile number) of the
 // contribution block with depth ns.
 // Modes 0 / 1 with nseg > 1 split the depth into segments of segk columns (a
 // multiple of 16) whose partial products go to part (bt.sP elements per batch:
-// count * nseg * kTile^2 needed); launch_gemm_reduce then applies them.
+// count * nseg * kTile^2 needed); launch_gemm_reduce then applies them.  A mode-1
+// task (front, row | kLaFlag) is the diagonal block of tile t + 1 at depth t * kNB.
 template <typename T>
 void launch_gemm_lt(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t, int mode,
                     int nseg, int segk, const Batch& bt, int nb, T* L, T* U, const T* W, T* part,

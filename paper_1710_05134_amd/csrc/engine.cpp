@@ -228,26 +228,29 @@ static void build_schedule(Pencil& P) {
         for (int64_t r = k0 + kb + kTrsmRows; r < nf; r += kTrsmRows) { sched.push_back(s); sched.push_back((int32_t)r); }
       }
       sp.trsm2_cnt = (int32_t)((sched.size() - sp.trsm2_off) / 2);
-      // left-looking update of this tile's column block (steps after the first):
-      // its diagonal block, then rows below it in kTile chunks
-      sp.ll_diag_off = (int32_t)sched.size();
-      if (t > 0)
-        for (int32_t q = 0; q < act; q++) { sched.push_back(large[q]); sched.push_back((int32_t)(t * kNB)); }
-      sp.ll_diag_cnt = (int32_t)((sched.size() - sp.ll_diag_off) / 2);
+      // left-looking update at depth t * kNB (steps after the first): the rows below
+      // this tile in kTile chunks and, ahead of the next tile, its diagonal block
+      // (the columns of tile t reach that block in the panel solve of step t)
       sp.ll_rest_off = (int32_t)sched.size();
+      if (t > 0) {
+        // the next tile's diagonal block at this depth (the next tile's fronts: a
+        // prefix of the list), then the rows below this tile
+        int32_t act_next = 0;
+        while (act_next < (int32_t)large.size() && S.ns(large[act_next]) > (t + 1) * kNB) act_next++;
+        for (int32_t q = 0; q < act_next; q++) {
+          sched.push_back(large[q]);
+          sched.push_back((int32_t)((t + 1) * kNB) | kLaFlag);
+        }
+      }
       if (t > 0)
         for (int32_t q = 0; q < act; q++) {
           const int32_t s = large[q];
           for (int64_t r = t * kNB + kTile; r < S.nf(s); r += kTile) { sched.push_back(s); sched.push_back((int32_t)r); }
         }
       sp.ll_rest_cnt = (int32_t)((sched.size() - sp.ll_rest_off) / 2);
-      // depth t * kNB: kSegK-deep segments for the rows below; shorter ones for the
-      // diagonal block (its update precedes the tile factorization), at least
-      // kSegKDiag deep and at most kMaxSegDiag of them (the ordered reduction
-      // reads each)
       const int64_t depth = (int64_t)t * kNB;
-      // rows below: as many segments (each at least kSegK deep, a multiple of 16) as
-      // bring the launch to about ll_wgs workgroups
+      // as many depth segments (each at least kSegK deep, a multiple of 16) as bring
+      // the launch to about ll_wgs workgroups
       {
         const int64_t most = std::max<int64_t>(1, (depth + kSegK - 1) / kSegK);
         const int64_t want = (ll_wgs + std::max<int64_t>(sp.ll_rest_cnt, 1) - 1) /
@@ -256,13 +259,8 @@ static void build_schedule(Pencil& P) {
         sp.ll_segk = (int32_t)std::max<int64_t>(kSegK, ((depth + ns_ - 1) / ns_ + 15) / 16 * 16);
         sp.ll_nseg = std::max<int32_t>(1, (int32_t)((depth + sp.ll_segk - 1) / sp.ll_segk));
       }
-      sp.ll_segk_d = (int32_t)std::max<int64_t>(
-          kSegKDiag, ((depth + kMaxSegDiag - 1) / kMaxSegDiag + 15) / 16 * 16);
-      sp.ll_nseg_d = std::max<int32_t>(1, (int32_t)((depth + sp.ll_segk_d - 1) / sp.ll_segk_d));
       if (sp.ll_nseg > 1)
         P.psize = std::max<int64_t>(P.psize, (int64_t)sp.ll_rest_cnt * sp.ll_nseg * kTile * kTile);
-      if (sp.ll_nseg_d > 1)
-        P.psize = std::max<int64_t>(P.psize, (int64_t)sp.ll_diag_cnt * sp.ll_nseg_d * kTile * kTile);
       lp.steps.push_back(sp);
     }
     // contribution blocks: lower tiles of each nu x nu block (depth ns), 64 x 64 or,
@@ -735,14 +733,16 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
       launch_front_init(P.meta, reinterpret_cast<const Int2*>(sched + lp.init_off), lp.init_cnt, av,
                         bv, bt, nb, Lf, Uf, st);
     }
-    // Left-looking steps with look-ahead: after the panel solve of step q, the
-    // column block of tile q+1 is brought up to date (its diagonal block first);
-    // tile q+1 is factored on the auxiliary stream while the rows below it are
-    // updated on the context stream.  Contribution blocks follow the last step.
+    // Left-looking steps with look-ahead: the panel solve of tile q's next rows
+    // finishes the diagonal block of tile q+1 (its columns < q*kNB were applied a
+    // step earlier); tile q+1 is factored on the auxiliary stream while the rest
+    // of tile q's rows are solved and the rows below tile q+1 (and, ahead, the
+    // diagonal block of tile q+2) are updated on the context stream.
+    // Contribution blocks follow the last step.
     // per step: operation counts and, for the column-block update, its algorithmic
     // bytes (each C entry read and written once, the depth-k0 rows of L below and
     // of W in the tile read once; diagonal-block counts are kept apart)
-    struct StepCost { double tile = 0, trsm = 0, ll = 0, ll_bytes = 0, lld = 0, lld_bytes = 0; };
+    struct StepCost { double tile = 0, trsm = 0, ll = 0, ll_bytes = 0, lld = 0, lla = 0, lla_bytes = 0; };
     auto step_cost = [&](const StepPlan& sp) {
       StepCost c;
       if (!prof) return c;
@@ -755,9 +755,11 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
         c.trsm += R * (kb * kb + kb);      // R rows: triangular solve + diagonal scaling
         const double rd = std::min<double>(kTile, nf - k0);   // rows of the diagonal task
         const double ed = kb * rd - kb * (kb - 1) / 2, er = kb * (nf - k0 - rd);
+        const double ka = std::max<double>(0.0, k0 - kNB);   // depth of the look-ahead part
         c.lld += 2.0 * k0 * ed;
+        c.lla += 2.0 * ka * ed;
         c.ll += 2.0 * k0 * er;
-        c.lld_bytes += 16.0 * ed + 8.0 * k0 * (rd + kb);
+        c.lla_bytes += 16.0 * ed + 8.0 * ka * (rd + kb);
         c.ll_bytes += 16.0 * er + 8.0 * k0 * ((nf - k0 - rd) + kb);
       }
       return c;
@@ -765,19 +767,22 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
     for (size_t q = 0; q < lp.steps.size(); q++) {
       const StepPlan& sp = lp.steps[q];
       const StepCost cs = step_cost(sp);
-      const double fl_tile = cs.tile, fl_trsm = cs.trsm;
+      const bool has_next = q + 1 < lp.steps.size();
+      const StepCost cn = has_next ? step_cost(lp.steps[q + 1]) : StepCost{};
       if (q == 0) {
-        ProfScope ps(prof, st, PROF_TILE, fl_tile);
+        ProfScope ps(prof, st, PROF_TILE, cs.tile);
         launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, bt, nb, Lf,
                            F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), st);
       } else {
         KTH_HIP(hipStreamWaitEvent(st, c->ev_tile, 0));   // tile q, factored ahead
       }
       {
-        ProfScope ps(prof, st, PROF_TRSM, fl_trsm);
+        // the next tile's rows, which also apply this tile's columns to the next
+        // diagonal block (the rest of its update was applied during this tile)
+        ProfScope ps(prof, st, PROF_TRSM, cs.trsm + (cn.lld - cn.lla));
         launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm_off), sp.trsm_cnt,
                           sp.t, bt, nb, Lf, Wf, F.D.get(), F.E.get(), F.tperm.get(),
-                          Tf, F.stats.get(), st);
+                          Tf, F.stats.get(), 1, st);
       }
       // the rest of the panel solve: after the next tile is handed to the second
       // stream (it reads tile t's inverse from the slot of t's parity)
@@ -785,23 +790,12 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
         ProfScope ps(prof, st, PROF_TRSM, 0.0);
         launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm2_off), sp.trsm2_cnt,
                           sp.t, bt, nb, Lf, Wf, F.D.get(), F.E.get(), F.tperm.get(),
-                          Tf, F.stats.get(), st);
+                          Tf, F.stats.get(), 0, st);
       };
-      if (q + 1 == lp.steps.size()) trsm_rest();
-      if (q + 1 < lp.steps.size()) {
+      if (!has_next) trsm_rest();
+      if (has_next) {
         const StepPlan& nx = lp.steps[q + 1];
-        const StepCost cn = step_cost(nx);
-        const Int2* dtask = reinterpret_cast<const Int2*>(sched + nx.ll_diag_off);
         const Int2* rtask = reinterpret_cast<const Int2*>(sched + nx.ll_rest_off);
-        {
-          ProfScope ps(prof, st, PROF_GEMM, cn.lld, cn.lld_bytes);
-          launch_gemm_lt(P.meta, dtask, nx.ll_diag_cnt, nx.t, 0, nx.ll_nseg_d, nx.ll_segk_d, bt, nb, Lf, Uf,
-                         Wf, Pf, st);
-        }
-        if (nx.ll_nseg_d > 1) {
-          ProfScope ps(prof, st, PROF_REDUCE, 0.0);
-          launch_gemm_reduce(P.meta, dtask, nx.ll_diag_cnt, nx.t, nx.ll_nseg_d, bt, nb, Lf, Pf, st);
-        }
         KTH_HIP(hipEventRecord(c->ev_diag, st));
         KTH_HIP(hipStreamWaitEvent(c->aux, c->ev_diag, 0));
         {
@@ -812,9 +806,12 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
         KTH_HIP(hipEventRecord(c->ev_tile, c->aux));
         trsm_rest();
         {
-          ProfScope ps(prof, st, PROF_GEMM, cn.ll, cn.ll_bytes);
-          launch_gemm_lt(P.meta, rtask, nx.ll_rest_cnt, nx.t, 1, nx.ll_nseg, nx.ll_segk, bt, nb, Lf, Uf, Wf, Pf,
-                         st);
+          // the rows below tile q + 1 and, ahead, the diagonal block of tile q + 2 at
+          // the same depth (columns of tiles <= q; tile q's rows there were just solved)
+          const StepCost c2 = q + 2 < lp.steps.size() ? step_cost(lp.steps[q + 2]) : StepCost{};
+          ProfScope ps(prof, st, PROF_GEMM, cn.ll + c2.lla, cn.ll_bytes + c2.lla_bytes);
+          launch_gemm_lt(P.meta, rtask, nx.ll_rest_cnt, nx.t, 1, nx.ll_nseg, nx.ll_segk, bt, nb, Lf, Uf,
+                         Wf, Pf, st);
         }
         if (nx.ll_nseg > 1 && nx.ll_rest_cnt > 0) {
           ProfScope ps(prof, st, PROF_REDUCE, 0.0);

@@ -104,11 +104,11 @@ struct StepPlan {
   int32_t nfronts;     // active large fronts (prefix of the level's sorted list)
   int32_t trsm_off, trsm_cnt;        // Int2 (front, row) panel-solve tasks of the next tile's rows
   int32_t trsm2_off, trsm2_cnt;      // ... of the rows below those (offsets in int32 units)
-  int32_t ll_diag_off, ll_diag_cnt;  // Int2 (front, k0): the tile's diagonal block (t > 0)
-  int32_t ll_rest_off, ll_rest_cnt;  // Int2 (front, row): rows below it (t > 0)
+  int32_t ll_rest_off, ll_rest_cnt;  // Int2 (front, row): rows below it (t > 0), after the
+                                     // tasks (front, row | kLaFlag) of the next tile's
+                                     // diagonal block at the same depth
   int32_t ll_nseg;                   // depth segments of the rows-below update
   int32_t ll_segk;                   // their depth (>= kSegK, a multiple of 16)
-  int32_t ll_nseg_d, ll_segk_d;      // depth segments of the diagonal-block update, their depth
 };
 
 struct LevelPlan {

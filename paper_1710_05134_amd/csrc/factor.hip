@@ -6,16 +6,19 @@
 //     assemble originals fma(-sigma, b, a), add children's update blocks, then
 //     unblocked Bunch-Kaufman over the fully-summed columns, write the panel,
 //     D and the update block.
-//   * larger fronts: k_front_init assembles column chunks in HBM (each entry
-//     written once: children's contributions gathered through inverse maps, then
-//     the original entries added); then per pivot tile of kNB columns:
-//     k_tile_factor (Bunch-Kaufman inside the tile), k_panel_trsm (rows
+//   * larger fronts: k_front_init assembles pieces of 16 columns x 512 rows in
+//     HBM (each entry written once: children's contributions gathered through
+//     inverse maps, then the original entries added); then per pivot tile of kNB
+//     columns: k_tile_factor (Bunch-Kaufman inside the tile), k_panel_trsm (rows
 //     below the tile: L21 = S21 P^T L11^{-T} D^{-1}, and W = L21 D kept
 //     panel-shaped); the column block of each tile is first brought up to date
 //     left-looking, C -= L(:, <k0) W(tile rows, <k0)^T on FP64 MFMA (k_gemm_lt),
 //     and once all tiles are done the contribution block receives
-//     -L_u W_u^T with depth ns in one product.  The host runs the next tile's
-//     factorization on a second stream once its diagonal block is updated.
+//     -L_u W_u^T with depth ns in one product.  The next tile's diagonal block
+//     gets the columns before the current tile ahead, in the same launch as the
+//     current column block's rows, and the current tile's columns in the panel
+//     solve of the next tile's rows; the host then runs the next tile's
+//     factorization on a second stream.
 // Row interchanges stay inside a tile; rows of earlier panels are not swapped --
 // the solve applies each tile's permutation when it reaches that tile.
 #include <hip/hip_runtime.h>
@@ -867,6 +870,9 @@ __device__ __forceinline__ void lds_read_chunk(uint32_t ba, uint32_t bb, float (
 //   W = S P^T L_tt^{-T}  (MFMA, with the tile inverse from k_tile_factor)
 //   L21 = W D^{-1}       (1x1 / 2x2 blocks)
 // The panel rows receive L21, the W panel (same layout) receives W (= L21 D).
+// With upd, the task of the next tile's rows (r0 < ns) then also subtracts this
+// tile's part of the next diagonal block's update, L W^T over kNB columns, from
+// the values it holds in LDS.
 // ---------------------------------------------------------------------------
 template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* tasks, int t,
@@ -875,7 +881,7 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
                                                    const double* __restrict__ E,
                                                    const int32_t* __restrict__ tperm,
                                                    const T* __restrict__ tinv,
-                                                   FactStats* st) {
+                                                   FactStats* st, int upd) {
   {
     const int64_t bidx = blockIdx.y;
     L += bidx * bt.sL; W += bidx * bt.sW; D += bidx * bt.sN; E += bidx * bt.sN;
@@ -903,6 +909,25 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
     pp[q] = q < kb ? tperm[f0 + k0 + q] : 0;
   }
   const int nr = min(kTile, nf - r0);
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // with upd on the next tile's rows: that tile's diagonal block (kb2 columns), the
+  // entries this thread updates at the end, loaded now (its earlier depth is in)
+  const bool nxt = upd && r0 < ns;
+  const int kb2 = nxt ? min(kNB, ns - r0) : 0;
+  T* Cb = Lp + r0 + (int64_t)r0 * nf;
+  T cpre[2][2][4];
+  if (nxt) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int i = wr + a * 16 + MF<T>::mrow(r, lane), j = wc + b * 16 + (lane & 15);
+          cpre[a][b][r] = (i < nr && j < kb2 && i >= j) ? Cb[i + (int64_t)j * nf] : (T)0.0;
+        }
+  }
   __syncthreads();   // pp[] visible
   {
     constexpr int U = kTile * kNB / NT;   // 16 loads of each operand per thread, all in flight
@@ -921,8 +946,6 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
     }
   }
   __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   typename MF<T>::acc acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; a++)
@@ -953,7 +976,10 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
   double maxl = 0.0;
   for (int x = tid; x < kTile * kNB; x += NT) {
     const int r = x % kTile, q = x / kTile;
-    if (r >= nr || q >= kb) continue;
+    if (r >= nr || q >= kb) {
+      Bs[x] = 0.0;
+      continue;
+    }
     const T wq = As[r + q * kTile];
     T l;
     if (q + 1 < kb && ee[q] != 0.0) {            // first row of a 2x2 block
@@ -967,7 +993,40 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
     }
     Lp[(r0 + r) + (int64_t)(k0 + q) * nf] = l;
     Wp[(r0 + r) + (int64_t)(k0 + q) * nf] = wq;
+    Bs[x] = l;   // L(r0 + r, k0 + q) at r + q * kTile (the inverse is no longer read)
     maxl = fmax(maxl, fabs((double)l));
+  }
+  if (nxt) {
+    // these rows are the next tile's: its diagonal block C (rows and columns r0 ..,
+    // lower part, kb2 columns) receives this tile's columns, C -= L W^T over the
+    // kb (= kNB) columns just solved; the depth before k0 reached it beforehand
+    __syncthreads();   // Bs (L) and As (W) complete
+    typename MF<T>::acc xc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++) xc[a][b] = MF<T>::zero();
+    for (int q0 = 0; q0 < kNB; q0 += 4) {
+      T av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; a++) av[a] = Bs[(wr + a * 16 + m) + (q0 + kk) * kTile];
+#pragma unroll
+      for (int b = 0; b < 2; b++) bv[b] = As[(wc + b * 16 + m) + (q0 + kk) * kTile];
+#pragma unroll
+      for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) xc[a][b] = MF<T>::step(av[a], bv[b], xc[a][b]);
+    }
+    // xc[a][b][r]: i = wr + a * 16 + mrow(r, lane) (row of L), j = wc + b * 16 + lane % 16
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int i = wr + a * 16 + MF<T>::mrow(r, lane), j = wc + b * 16 + (lane & 15);
+          if (i < nr && j < kb2 && i >= j) Cb[i + (int64_t)j * nf] = cpre[a][b][r] - xc[a][b][r];
+        }
   }
   maxl = block_max<NT>(maxl, sv);
   if (tid == 0) atomicMax(&st->max_l_bits, dbits(maxl));
@@ -978,6 +1037,8 @@ __global__ __launch_bounds__(NT) void k_panel_trsm(FrontMeta M, const Int2* task
 //   mode 0 / 1, column block of pivot tile t, rows [i0, i0 + kTile) (mode 0: the
 //     tile's own diagonal block, lower part; mode 1: rows below it):
 //       C(i, j) -= sum_{q < k0} L(i, q) W(j, q),   j in [k0, k0 + kb)
+//     (a mode-1 task (front, row | kLaFlag): the diagonal block of tile t + 1,
+//     columns [k0 + kNB, ..), the same depth k0)
 //   mode 2, the contribution block, lower 64 x 64 tile number b of it:
 //       U(i, j) -= sum_{q < ns} L(ns + i, q) W(ns + j, q),   i >= j
 // W = L D is kept panel-shaped (same offsets and ld as L) by k_panel_trsm.  The
@@ -1016,8 +1077,10 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
   int64_t ldc;
   int Kb = 0;              // first depth column of this workgroup
   if (mode < 2) {
-    const int k0 = t * kNB, kb = min(kNB, f.ns - k0);
-    ia = tk.b; ie = min(ia + kTile, f.nf); ja = k0; je = k0 + kb; K = k0;
+    // a flagged task: the diagonal block of tile t + 1, still at depth t * kNB
+    const bool la = (tk.b & kLaFlag) != 0;
+    const int k0 = (t + (la ? 1 : 0)) * kNB, kb = min(kNB, f.ns - k0);
+    ia = tk.b & ~kLaFlag; ie = min(ia + kTile, f.nf); ja = k0; je = k0 + kb; K = t * kNB;
     if (nseg > 1) { Kb = seg * segk; K = min(K, Kb + segk); }
     tri = (ia == k0);
     Cb = f.Lp + ia + (int64_t)ja * f.nf; ldc = f.nf;
@@ -1168,8 +1231,9 @@ __global__ __launch_bounds__(NT) void k_gemm_reduce(FrontMeta M, const Int2* tas
   const int64_t f0 = M.sfirst[s];
   const int ns = (int)(M.sfirst[s + 1] - f0);
   const int nf = (int)(M.rptr[s + 1] - M.rptr[s]);
-  const int k0 = t * kNB, kb = min(kNB, ns - k0);
-  const int ia = tk.b, ie = min(ia + kTile, nf);
+  const bool la = (tk.b & kLaFlag) != 0;   // the diagonal block of tile t + 1
+  const int k0 = (t + (la ? 1 : 0)) * kNB, kb = min(kNB, ns - k0);
+  const int ia = tk.b & ~kLaFlag, ie = min(ia + kTile, nf);
   const bool tri = (ia == k0);
   const int i = x % kTile, j = x / kTile;
   if (ia + i >= ie || j >= kb || (tri && i < j)) return;
@@ -1441,10 +1505,10 @@ void launch_tile_factor(const FrontMeta& M, const int32_t* fronts, int32_t count
 template <typename T>
 void launch_panel_trsm(const FrontMeta& M, const Int2* tasks, int32_t count, int32_t t,
                        const Batch& bt, int nb, T* L, T* W, const double* D, const double* E,
-                       const int32_t* tperm, const T* tinv, FactStats* st, hipStream_t s) {
+                       const int32_t* tperm, const T* tinv, FactStats* st, int upd, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL((k_panel_trsm<256, T>), dim3(count, nb), dim3(256), 0, s, M, tasks, t, bt, L, W,
-                     D, E, tperm, tinv, st);
+                     D, E, tperm, tinv, st, upd);
 }
 
 template <typename T>
@@ -1483,7 +1547,7 @@ void launch_gemm_reduce(const FrontMeta& M, const Int2* tasks, int32_t count, in
                                       FactStats*, hipStream_t);                                     \
   template void launch_panel_trsm<T>(const FrontMeta&, const Int2*, int32_t, int32_t, const Batch&, \
                                      int, T*, T*, const double*, const double*, const int32_t*,     \
-                                     const T*, FactStats*, hipStream_t);                            \
+                                     const T*, FactStats*, int, hipStream_t);                       \
   template void launch_gemm_lt<T>(const FrontMeta&, const Int2*, int32_t, int32_t, int, int, int,    \
                                   const Batch&, int, T*, T*, const T*, T*, hipStream_t);            \
   template void launch_gemm_cb128<T>(const FrontMeta&, const Int2*, int32_t, const Batch&, int, T*,  \
