@@ -569,6 +569,18 @@ void factor_alloc(Pencil& P, NumFactor& F, int nb, kth_precision prec) {
     ensure_workspace(P, nb);
     return;
   }
+  // a new layout (pencil, batch or precision): captured launch sequences belong to
+  // the old one -- its kernels may be of the other precision even where the new
+  // buffers land at the old addresses -- so they are dropped
+  if (F.graphs[0].exec || F.graphs[1].exec) {
+    KTH_HIP(hipStreamSynchronize(c->stream));
+    for (FactorGraph& g : F.graphs)
+      if (g.exec) {
+        (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.nb = 0;
+      }
+  }
   F.p = &P;
   F.nb = nb;
   F.prec = prec;

@@ -203,3 +203,28 @@ def test_eig_fp32_n524k_matches_fp64(K, ctx):
     assert abs(x32 @ (B @ x64)) >= 1 - 1e-8            # the same B-normalised vector
     d = 1e-10 * nA
     assert P.nu(lam32 - d) < p.k <= P.nu(lam32 + d)
+
+
+def test_eig_precision_switch_same_pencil(K):
+    # the shift-and-invert factor of one pencil alternates FP64 / FP32 + IR: each
+    # change of precision re-lays the factor out, and a launch sequence captured for
+    # the other precision must not be replayed on it (the new buffers can land at
+    # the old addresses -- likely in a fresh context, whose cache holds just them)
+    c = K.Context(0)
+    p = pg.tb_supercell((3, 3, 3), seed=0)
+    k = p.n // 2
+    sv = pg.start_vectors(p.n, seed=0)
+    lam_ref, _ = od.kth(p, k)
+    nA = od.norm_inf(p)
+    P = K.Pencil.from_pencilgen(c, p)
+    for prec in (K.KTH_FP64, K.KTH_FP32_IR, K.KTH_FP64, K.KTH_FP32_IR):
+        lam, x, info = P.eig(k, start_vectors=sv, si_precision=prec)
+        note(f"precision switch: si_precision {prec} -> lambda {lam!r}, fallback "
+             f"{info['ir_fallback']}, ir_steps {info['ir_steps']}")
+        assert info["k_validated"] == k
+        assert info["si_precision"] == prec and info["ir_fallback"] == 0
+        assert abs(lam - lam_ref) <= 1e-10 * nA
+        r = p.A() @ x - lam * (p.B() @ x)
+        assert np.linalg.norm(r) / (nA * np.linalg.norm(x)) <= 1e-9
+    P.close()
+    c.close()
