@@ -455,11 +455,8 @@ __device__ void bk_tile_regs(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, B
     }
     if (kind < 2) {
       const T dk = pv[par][0];
-      if (tid == 0) {
-        d[k] = dk; e[k] = 0.0;
-        if (dk < 0) cnt.neg++; else if (dk > 0) cnt.pos++; else cnt.zero++;
-        cnt.mind = fmin(cnt.mind, fabs((double)dk));
-      }
+      // the 1x1 pivots' signs and magnitudes are counted after the loop, from d
+      if (tid == 0) { d[k] = dk; e[k] = 0.0; }
       if (dk != 0.0) {
         const bool act = i > k && i < kb;
         const T li = act ? yb[par][0][i] / dk : (T)0.0;
@@ -467,7 +464,8 @@ __device__ void bk_tile_regs(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, B
         // outside k < i < kb; entries above the diagonal take values never read
 #pragma unroll
         for (int m = 0; m < NM; m++) R[m] = R[m] - li * yb[par][0][4 * m + wave];
-        if (wave == 0 && act) { Lo[i + k * ld] = li; maxl = fmax(maxl, fabs((double)li)); }
+        // multipliers: by the wave that published column k (not the next column's)
+        if (wave == (k & 3) && act) { Lo[i + k * ld] = li; maxl = fmax(maxl, fabs((double)li)); }
       }
       k += 1;
     } else {
@@ -497,7 +495,7 @@ __device__ void bk_tile_regs(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, B
         const T u1 = j > k + 1 ? yb[par][0][j] : (T)0.0;
         R[m] = R[m] - (l1 * u1 + l2 * yb[par][1][j]);
       }
-      if (wave == 0 && act) {
+      if (wave == (k & 3) && act) {
         Lo[i + k * ld] = l1;
         Lo[i + (k + 1) * ld] = l2;
         maxl = fmax(maxl, fmax(fabs((double)l1), fabs((double)l2)));
@@ -506,9 +504,26 @@ __device__ void bk_tile_regs(T* F, T* Lo, int ld, int kb, int* lp, T* d, T* e, B
     }
     par ^= 1;
   }
+  // 1x1 pivots (e = 0 here and before): counts by sign and the least magnitude, the
+  // same tallies the steps would have made; largest multiplier over all waves
+  __shared__ double mx[4];
+  for (int off = 32; off > 0; off >>= 1) maxl = fmax(maxl, __shfl_xor(maxl, off));
+  if (lane == 0) mx[wave] = maxl;
+  __syncthreads();   // d, e and mx complete
   if (wave == 0) {
-    for (int off = 32; off > 0; off >>= 1) maxl = fmax(maxl, __shfl_xor(maxl, off));
-    if (lane == 0) cnt.maxl = fmax(cnt.maxl, maxl);
+    const bool one = i < kb && e[i] == 0.0 && (i == 0 || e[i - 1] == 0.0);
+    const T di = one ? d[i] : (T)0.0;
+    const unsigned long long neg = __ballot(one && di < 0), pos = __ballot(one && di > 0);
+    const unsigned long long zer = __ballot(one && di == 0);
+    double mn = one ? fabs((double)di) : (double)INFINITY;
+    for (int off = 32; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off));
+    if (lane == 0) {
+      cnt.neg += __popcll(neg);
+      cnt.pos += __popcll(pos);
+      cnt.zero += __popcll(zer);
+      cnt.mind = fmin(cnt.mind, mn);
+      cnt.maxl = fmax(cnt.maxl, fmax(fmax(mx[0], mx[1]), fmax(mx[2], mx[3])));
+    }
   }
 }
 
