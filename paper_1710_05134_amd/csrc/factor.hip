@@ -1206,25 +1206,41 @@ __global__ __launch_bounds__(NT) void k_gemm_lt(FrontMeta M, const Int2* tasks, 
           P[(wr + a * 16 + il) + (wc + b * 16 + MF<T>::mrow(r, lane)) * kTile] = acc[a][b][r];
     return;
   }
-  // C -= product, read after the depth loop (keeps the loop's registers free)
+  // C -= product, read after the depth loop (keeps the loop's registers free): the
+  // 16 entries of C in one batch (indices clamped into the block, so every read is
+  // valid; only entries inside it are written), then the writes
+  const int im = ie - ia - 1, jm = je - ja - 1;
+  T cv[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++) {
-      T cv[4];
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int i = min(wr + a * 16 + il, im), j = min(wc + b * 16 + MF<T>::mrow(r, lane), jm);
+        cv[a][b][r] = Cb[i + (int64_t)j * ldc];
+      }
+  // the new values are formed before any (masked) write, so no write waits on the
+  // reads or on the writes before it
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        cv[a][b][r] = cv[a][b][r] - acc[a][b][r];
+        asm volatile("" : "+v"(cv[a][b][r]));
+      }
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
         const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || ia + i >= ja + j);
-        cv[r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
+        if (ok) Cb[i + (int64_t)j * ldc] = cv[a][b][r];
       }
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
-        const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || ia + i >= ja + j);
-        if (ok) Cb[i + (int64_t)j * ldc] = cv[r] - acc[a][b][r];
-      }
-    }
 }
 
 // C -= sum of the nseg depth segments of each output tile (in segment order) for
@@ -1428,25 +1444,46 @@ __global__ __launch_bounds__(NT, 2) void k_gemm_cb128(FrontMeta M, const Int2* t
       mult(As[v], Bs[v]);
     }
   }
-  // C -= product
+  // C -= product, in two halves of the wave's rows: each half's 32 entries of C are
+  // read in one batch (indices clamped into the block, so every read is valid; only
+  // entries inside it are written), then written -- two waits for reads per tile
+  // instead of one per 16 x 16 block
+  const int im = ie - ia - 1, jm = je - ja - 1;
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+  for (int h = 0; h < 2; h++) {
+    T cv[2][4][4];
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
-      T cv[4];
+    for (int a2 = 0; a2 < 2; a2++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
-        const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || i >= j);
-        cv[r] = ok ? Cb[i + (int64_t)j * ldc] : 0.0;
-      }
+      for (int b = 0; b < 4; b++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
-        const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || i >= j);
-        if (ok) Cb[i + (int64_t)j * ldc] = cv[r] - acc[a][b][r];
-      }
-    }
+        for (int r = 0; r < 4; r++) {
+          const int i = min(wr + (2 * h + a2) * 16 + il, im), j = min(wc + b * 16 + MF<T>::mrow(r, lane), jm);
+          cv[a2][b][r] = Cb[i + (int64_t)j * ldc];
+        }
+    // the new values are formed before any (masked) write, so no write waits on
+    // the reads or on the writes before it
+#pragma unroll
+    for (int a2 = 0; a2 < 2; a2++)
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          cv[a2][b][r] = cv[a2][b][r] - acc[2 * h + a2][b][r];
+          asm volatile("" : "+v"(cv[a2][b][r]));
+        }
+#pragma unroll
+    for (int a2 = 0; a2 < 2; a2++)
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int a = 2 * h + a2;
+          const int i = wr + a * 16 + il, j = wc + b * 16 + MF<T>::mrow(r, lane);
+          const bool ok = (ia + i < ie) && (ja + j < je) && (!tri || i >= j);
+          if (ok) Cb[i + (int64_t)j * ldc] = cv[a2][b][r];
+        }
+  }
 }
 
 __global__ void k_set_scalar(double* p, double v) {
