@@ -82,6 +82,7 @@ void Ctx::ensure_aux() {
   KTH_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
   KTH_HIP(hipEventCreateWithFlags(&ev_diag, hipEventDisableTiming));
   KTH_HIP(hipEventCreateWithFlags(&ev_tile, hipEventDisableTiming));
+  KTH_HIP(hipEventCreateWithFlags(&ev_main, hipEventDisableTiming));
 }
 
 void Ctx::ensure_workers(int nw) {
@@ -115,6 +116,7 @@ void Ctx::destroy_aux() {
   (void)hipStreamSynchronize(aux);
   (void)hipEventDestroy(ev_diag);
   (void)hipEventDestroy(ev_tile);
+  (void)hipEventDestroy(ev_main);
   (void)hipStreamDestroy(aux);
   aux = nullptr;
 }
@@ -747,10 +749,9 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
     }
     // Left-looking steps with look-ahead: the panel solve of tile q's next rows
     // finishes the diagonal block of tile q+1 (its columns < q*kNB were applied a
-    // step earlier); tile q+1 is factored on the auxiliary stream while the rest
-    // of tile q's rows are solved and the rows below tile q+1 (and, ahead, the
-    // diagonal block of tile q+2) are updated on the context stream.
-    // Contribution blocks follow the last step.
+    // step earlier); tile q+1 is factored while the rest of tile q's rows are
+    // solved and the rows below tile q+1 (and, ahead, the diagonal block of tile
+    // q+2) are updated.  Contribution blocks follow the last step.
     // per step: operation counts and, for the column-block update, its algorithmic
     // bytes (each C entry read and written once, the depth-k0 rows of L below and
     // of W in the tile read once; diagonal-block counts are kept apart)
@@ -776,47 +777,59 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
       }
       return c;
     };
+    // The chain of a level runs on the auxiliary stream: tile q's factorization,
+    // the panel solve of its next rows (which finishes tile q+1's diagonal block),
+    // tile q+1's factorization, ...; each next-rows solve also waits for the
+    // context stream's previous step (the rows below tile q, the look-ahead
+    // diagonal block).  The context stream solves the rest of tile q's rows and
+    // updates the rows below tile q+1 (and, ahead, tile q+2's diagonal block).
+    KTH_HIP(hipEventRecord(c->ev_main, st));   // the level's fronts assembled
+    KTH_HIP(hipStreamWaitEvent(c->aux, c->ev_main, 0));
+    if (!lp.steps.empty()) {
+      const StepPlan& s0 = lp.steps[0];
+      ProfScope ps(prof, c->aux, PROF_TILE, step_cost(s0).tile);
+      launch_tile_factor(P.meta, sched + lp.large_off, s0.nfronts, s0.t, bt, nb, Lf,
+                         F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), c->aux);
+    }
+    KTH_HIP(hipEventRecord(c->ev_tile, c->aux));
     for (size_t q = 0; q < lp.steps.size(); q++) {
       const StepPlan& sp = lp.steps[q];
       const StepCost cs = step_cost(sp);
       const bool has_next = q + 1 < lp.steps.size();
       const StepCost cn = has_next ? step_cost(lp.steps[q + 1]) : StepCost{};
-      if (q == 0) {
-        ProfScope ps(prof, st, PROF_TILE, cs.tile);
-        launch_tile_factor(P.meta, sched + lp.large_off, sp.nfronts, sp.t, bt, nb, Lf,
-                           F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), st);
-      } else {
-        KTH_HIP(hipStreamWaitEvent(st, c->ev_tile, 0));   // tile q, factored ahead
+      if (q > 0) {   // the rows below tile q and tile q+1's earlier depth are in
+        KTH_HIP(hipEventRecord(c->ev_main, st));
+        KTH_HIP(hipStreamWaitEvent(c->aux, c->ev_main, 0));
       }
       {
         // the next tile's rows, which also apply this tile's columns to the next
         // diagonal block (the rest of its update was applied during this tile)
-        ProfScope ps(prof, st, PROF_TRSM, cs.trsm + (cn.lld - cn.lla));
+        ProfScope ps(prof, c->aux, PROF_TRSM, cs.trsm + (cn.lld - cn.lla));
         launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm_off), sp.trsm_cnt,
                           sp.t, bt, nb, Lf, Wf, F.D.get(), F.E.get(), F.tperm.get(),
-                          Tf, F.stats.get(), 1, st);
+                          Tf, F.stats.get(), 1, c->aux);
       }
-      // the rest of the panel solve: after the next tile is handed to the second
-      // stream (it reads tile t's inverse from the slot of t's parity)
-      auto trsm_rest = [&]() {
+      KTH_HIP(hipEventRecord(c->ev_diag, c->aux));
+      // the rest of the panel solve, after tile q is factored (it reads tile q's
+      // inverse from the slot of q's parity while tile q+1's is written)
+      KTH_HIP(hipStreamWaitEvent(st, c->ev_tile, 0));
+      if (has_next) {
+        const StepPlan& nx = lp.steps[q + 1];
+        ProfScope ps(prof, c->aux, PROF_TILE, cn.tile);
+        launch_tile_factor(P.meta, sched + lp.large_off, nx.nfronts, nx.t, bt, nb, Lf,
+                           F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), c->aux);
+      }
+      KTH_HIP(hipEventRecord(c->ev_tile, c->aux));
+      {
         ProfScope ps(prof, st, PROF_TRSM, 0.0);
         launch_panel_trsm(P.meta, reinterpret_cast<const Int2*>(sched + sp.trsm2_off), sp.trsm2_cnt,
                           sp.t, bt, nb, Lf, Wf, F.D.get(), F.E.get(), F.tperm.get(),
                           Tf, F.stats.get(), 0, st);
-      };
-      if (!has_next) trsm_rest();
+      }
+      KTH_HIP(hipStreamWaitEvent(st, c->ev_diag, 0));   // the next rows' L and W
       if (has_next) {
         const StepPlan& nx = lp.steps[q + 1];
         const Int2* rtask = reinterpret_cast<const Int2*>(sched + nx.ll_rest_off);
-        KTH_HIP(hipEventRecord(c->ev_diag, st));
-        KTH_HIP(hipStreamWaitEvent(c->aux, c->ev_diag, 0));
-        {
-          ProfScope ps(prof, c->aux, PROF_TILE, cn.tile);
-          launch_tile_factor(P.meta, sched + lp.large_off, nx.nfronts, nx.t, bt, nb, Lf,
-                             F.D.get(), F.E.get(), F.tperm.get(), Tf, F.stats.get(), c->aux);
-        }
-        KTH_HIP(hipEventRecord(c->ev_tile, c->aux));
-        trsm_rest();
         {
           // the rows below tile q + 1 and, ahead, the diagonal block of tile q + 2 at
           // the same depth (columns of tiles <= q; tile q's rows there were just solved)
@@ -831,6 +844,7 @@ static void factor_body(Pencil& P, NumFactor& F, int nb, const double* av, const
         }
       }
     }
+    KTH_HIP(hipStreamWaitEvent(st, c->ev_tile, 0));   // everything on the second stream
     // contribution blocks, operation counts and algorithmic bytes: C once; L_u and
     // W_u once
     auto cb_cost = [&](bool big, double& fl, double& by) {

@@ -43,10 +43,10 @@ struct Ctx {
   // factorizations replay a captured HIP graph of their launch sequence
   // (environment KTH_GRAPHS=0 at context creation: launch kernel by kernel)
   bool use_graphs = true;
-  // second stream for the pivot tile of the next step (look-ahead), and the two
-  // events that order it against the context stream
+  // second stream for the pivot tiles and the panel solves of their next rows (the
+  // critical path), and the events that order it against the context stream
   hipStream_t aux = nullptr;
-  hipEvent_t ev_diag = nullptr, ev_tile = nullptr;
+  hipEvent_t ev_diag = nullptr, ev_tile = nullptr, ev_main = nullptr;
   // contexts of the worker threads of kth_eig_batch (own streams, same device and
   // allocator); they live as long as this context, so buffers they allocate for a
   // pencil stay releasable
