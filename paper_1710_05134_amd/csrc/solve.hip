@@ -202,6 +202,31 @@ __device__ inline double apply_dinv(const double* __restrict__ D, const double* 
   return D[k] != 0.0 ? z[q] / D[k] : 0.0;
 }
 
+// The entries apply_dinv reads for pivot q of a tile (k = its index), loaded ahead
+// without depending on each other: d_k, e_k, d_{k+1}, e_{k-1}, d_{k-1} (zero where
+// apply_dinv does not read them).
+__device__ inline void dinv_load(const double* __restrict__ D, const double* __restrict__ E,
+                                 int64_t k, int q, int kb, double (&v)[5]) {
+  const bool in = q < kb;
+  v[0] = in ? D[k] : 1.0;
+  v[1] = in && q + 1 < kb ? E[k] : 0.0;
+  v[2] = in && q + 1 < kb ? D[k + 1] : 0.0;
+  v[3] = in && q > 0 ? E[k - 1] : 0.0;
+  v[4] = in && q > 0 ? D[k - 1] : 0.0;
+}
+// apply_dinv on values from dinv_load: the same cases and arithmetic.
+__device__ inline double dinv_apply(const double (&v)[5], const double* z, int q) {
+  if (v[1] != 0.0) {
+    const double a = v[0], b = v[1], c = v[2], det = a * c - b * b;
+    return (c * z[q] - b * z[q + 1]) / det;
+  }
+  if (v[3] != 0.0) {
+    const double a = v[4], b = v[3], c = v[0], det = a * c - b * b;
+    return (a * z[q] - b * z[q - 1]) / det;
+  }
+  return v[0] != 0.0 ? z[q] / v[0] : 0.0;
+}
+
 // Sum over the 64 lanes of a wavefront of v[0..63] (lane l holds row l's products
 // with 64 columns), by recursive halving: at offset h every lane keeps one half of
 // its block of columns and adds its partner's copy of that half.  On return lane l
@@ -259,6 +284,14 @@ __global__ __launch_bounds__(kChainThreads) void k_lfwd_step(FrontMeta M, const 
   const int i = r0 + rr;
   double va[16], vb[16], vc[16];
   double ra = 0.0, ri = 0.0;
+  // the workgroup that writes y = D^{-1} z for the two tiles at the end loads their
+  // D and E entries now, with everything else
+  const bool writer = r0 == (two ? k1 + kb1 : k1);
+  double dv0[5] = {1.0, 0.0, 0.0, 0.0, 0.0}, dv1[5] = {1.0, 0.0, 0.0, 0.0, 0.0};
+  if (writer && tid < 64) {
+    dinv_load(D, E, f0 + k0 + lane, lane, kb0, dv0);
+    if (two) dinv_load(D, E, f0 + k1 + lane, lane, kb1, dv1);
+  }
   // unconditional loads from clamped (valid) addresses, masked afterwards, so that
   // they are all in flight together
   if (tid < 64) {
@@ -333,13 +366,13 @@ __global__ __launch_bounds__(kChainThreads) void k_lfwd_step(FrontMeta M, const 
   }
   // the first chunk's workgroup: y = D^{-1} z and z itself (xe of the pivots is free
   // once the level's gather has read it)
-  if (r0 == (two ? k1 + kb1 : k1)) {
+  if (writer) {
     if (tid < kb0) {
-      ye[f0 + k0 + tid] = apply_dinv(D, E, z0, f0 + k0 + tid, tid, kb0);
+      ye[f0 + k0 + tid] = dinv_apply(dv0, z0, tid);
       xe[f0 + k0 + tid] = z0[tid];
     }
     if (two && tid < kb1) {
-      ye[f0 + k1 + tid] = apply_dinv(D, E, z1, f0 + k1 + tid, tid, kb1);
+      ye[f0 + k1 + tid] = dinv_apply(dv1, z1, tid);
       xe[f0 + k1 + tid] = z1[tid];
     }
   }
