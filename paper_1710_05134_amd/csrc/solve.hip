@@ -294,7 +294,13 @@ __global__ __launch_bounds__(kChainThreads) void k_lfwd_step(FrontMeta M, const 
   }
   // unconditional loads from clamped (valid) addresses, masked afterwards, so that
   // they are all in flight together
+  // the two tiles' interchanges and tile t's rows of R in stored order, loaded with
+  // the tile (the interchange is then applied by a lane shuffle, not a second load)
+  int tp1 = 0;
   if (tid < 64) {
+    const int tp0 = lane < kb0 ? tperm[f0 + k0 + lane] : 0;
+    const double rv0 = lane < kb0 ? Rs[k0 + lane] : 0.0;
+    tp1 = two && lane < kb1 ? tperm[f0 + k1 + lane] : 0;
     const int lc = min(lane, kb0 - 1);
     double Lv[kNB];
 #pragma unroll
@@ -302,7 +308,8 @@ __global__ __launch_bounds__(kChainThreads) void k_lfwd_step(FrontMeta M, const 
     // strictly lower part of the tile only, so that every step updates all lanes
 #pragma unroll
     for (int p = 0; p < kNB; p++) Lv[p] = (lane < kb0 && p < lane) ? Lv[p] : 0.0;
-    double zl = lane < kb0 ? Rs[k0 + tperm[f0 + k0 + lane]] : 0.0;
+    const double rp = __shfl(rv0, tp0);   // R(k0 + tperm(lane)), from lane tperm(lane)
+    double zl = lane < kb0 ? rp : 0.0;
 #pragma unroll
     for (int p = 0; p < kNB; p++) zl = fma(-Lv[p], lane_value(zl, p), zl);
     z0[lane] = zl;   // zero beyond kb0
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(kChainThreads) void k_lfwd_step(FrontMeta M, const 
       double Lw[kNB];
 #pragma unroll
       for (int p = 0; p < kNB; p++) Lw[p] = (lane < kb1 && p < lane) ? tl1[lane][p] : 0.0;
-      double zl = lane < kb1 ? r1[tperm[f0 + k1 + lane]] : 0.0;
+      double zl = lane < kb1 ? r1[tp1] : 0.0;
 #pragma unroll
       for (int p = 0; p < kNB; p++) zl = fma(-Lw[p], lane_value(zl, p), zl);
       z1[lane] = zl;
