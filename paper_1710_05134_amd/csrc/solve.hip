@@ -469,8 +469,10 @@ __global__ __launch_bounds__(kChainThreads) void k_lbwd_push(FrontMeta M, const 
   const int u = tid - 64, qr = u & 3, jj = u >> 2;
   const int j = c0 + jj;
   double va[16], vb[16], vc[16];
-  double yv = 0.0;
+  double yv = 0.0, yj = 0.0;
+  int tp0 = 0;   // tile t's interchanges (used after its chain), loaded early
   if (tid < 64) {
+    tp0 = lane < kb0 ? tperm[f0 + k0 + lane] : 0;
     if (two) {
       // row lane of tile t + 1 into LDS (coalesced loads), then column lane from it;
       // one wave: its LDS writes and reads complete in order
@@ -500,6 +502,8 @@ __global__ __launch_bounds__(kChainThreads) void k_lbwd_push(FrontMeta M, const 
         va[c] = (double)Lp[(k1 + min(qr * 16 + c, kb1 - 1)) + (int64_t)(k0 + min(jj, kb0 - 1)) * nf];
     }
     if (qr == 0 && jj < kb0) yv = ye[f0 + k0 + jj];
+    // the entry of y this thread updates at the end (no other access here touches it)
+    if (qr == 0 && j < k0) yj = ye[f0 + j];
     // this chunk's columns j < k0: 16 rows of each tile
     const int jc = min(j, max(k0 - 1, 0));
 #pragma unroll
@@ -534,12 +538,11 @@ __global__ __launch_bounds__(kChainThreads) void k_lbwd_push(FrontMeta M, const 
 #pragma unroll
     for (int p = 0; p < kNB; p++) Lc[p] = (p > lane && p < kb0) ? tl0[p][lane] : 0.0;
     double g = lane < kb0 ? yt[lane] : 0.0;
-    const int tp = lane < kb0 ? tperm[f0 + k0 + lane] : 0;
 #pragma unroll
     for (int p = kNB - 1; p >= 0; p--) g = fma(-Lc[p], lane_value(g, p), g);
     xs0[lane] = 0.0;
-    if (lane < kb0) xs0[tp] = g;
-    if (c0 == 0 && lane < kb0) xe[f0 + k0 + tp] = g;
+    if (lane < kb0) xs0[tp0] = g;
+    if (c0 == 0 && lane < kb0) xe[f0 + k0 + tp0] = g;
   }
   __syncthreads();
   if (tid >= 64) {
@@ -552,7 +555,7 @@ __global__ __launch_bounds__(kChainThreads) void k_lbwd_push(FrontMeta M, const 
     }
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);
-    if (qr == 0 && j < k0) ye[f0 + j] -= acc;
+    if (qr == 0 && j < k0) ye[f0 + j] = yj - acc;
   }
 }
 
