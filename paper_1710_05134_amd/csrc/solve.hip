@@ -410,6 +410,15 @@ __global__ __launch_bounds__(kL21Rows) void k_lfwd_l21(FrontMeta M, const Int2* 
   const T* Lp = L + M.lptr[s] + i;
   double acc = 0.0;
   int q = c0;
+  // 32 loads in flight per pass (8 passes for a full segment), the products
+  // accumulated in column order
+  for (; q + 32 <= c1; q += 32) {
+    double v[32];
+#pragma unroll
+    for (int u = 0; u < 32; u++) v[u] = (double)Lp[(int64_t)(q + u) * nf];
+#pragma unroll
+    for (int u = 0; u < 32; u++) acc = fma(v[u], z[q - c0 + u], acc);
+  }
   for (; q + 8 <= c1; q += 8) {
     double v[8];
 #pragma unroll
