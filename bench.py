@@ -297,7 +297,8 @@ def main():
         summarize(st, fe, wr, args.summary_command, args.summary_pmc_command)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (no path across GPUs is built); "
+                                   "--gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
